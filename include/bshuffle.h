@@ -1,0 +1,166 @@
+/*
+ * bshuffle.h -- C ABI of the MI355X bijective-shuffle library (libbshuffle.so).
+ *
+ * The operation (Mitchell, Stokes, Frank, Holmes, "Bandwidth-Optimal Random
+ * Shuffling for GPUs", arXiv 2106.06161):
+ *
+ *   - Sec. 4 and Algorithm 1 ("Bijection Shuffle"): to shuffle n items, pad
+ *     the index range to a power of two 2^k, evaluate a keyed bijection f on
+ *     every padded index i, keep the i whose image f(i) is < n, and give each
+ *     kept i the output slot rank(i) = number of kept indices below i (an
+ *     exclusive scan of the keep flags).  The result is
+ *         out[rank(i)] = in[f(i)]      for every kept i.
+ *     Here k = max(ceil(log2 n), 4).
+ *   - Sec. 3.2 (VariablePhilox): f is a Feistel cipher on k-bit blocks with
+ *     a Philox-style multiply round; `rounds` rounds, each with its own
+ *     32-bit round key.  The paper recommends 24 rounds (Sec. 5).
+ *   - Sec. 7: the shuffle is parameterised by the bijection and a key of
+ *     rounds x log(n) bits.  This library derives the round keys from one
+ *     64-bit seed: key r = low 32 bits of the r-th SplitMix64 output started
+ *     at the seed.
+ *
+ * The output is a pure function of (input bytes, n, elem_bytes, seed, rounds):
+ * launch configuration, workspace, stream and batching never change a byte.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named in/out/offsets/seeds/workspace are DEVICE pointers
+ *     (hipMalloc / torch CUDA-tensor memory) on the current HIP device.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the legacy
+ *     default stream.  Work is enqueued asynchronously on it; argument errors
+ *     are returned synchronously before anything is enqueued, device-side
+ *     problems are reported through bs_workspace_error().
+ *   - No entry point throws; each returns a bs_status.
+ *   - The caller owns every buffer it passes.  The library owns only its
+ *     internal per-(device, stream) workspace cache, released at process exit.
+ */
+#ifndef BSHUFFLE_H
+#define BSHUFFLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bs_status;
+
+#define BS_OK 0        /* success                                              */
+#define BS_EINVAL 1    /* null pointer, bad size, bad rounds or bad workspace  */
+#define BS_EALIAS 2    /* in and out overlap (the method is out-of-place, Sec. 7) */
+#define BS_EELEM 3     /* elem_bytes not in {1,2,4,8,16}, or a pointer not aligned to it */
+#define BS_ENOMEM 4    /* workspace too small, or the internal cache could not grow */
+#define BS_EHIP 5      /* a HIP runtime call or launch failed; see bs_last_hip_error() */
+#define BS_ETIMEOUT 6  /* a look-back wait hit its spin limit (device side)     */
+#define BS_ENODEV 7    /* no HIP device is available                           */
+#define BS_EDEVICE 8   /* the device rejected the batch description (bad offsets, too many tiles) */
+
+#define BS_MAX_ROUNDS 64u
+/* Largest n: tile prefixes are packed into 38 bits of a status word. */
+#define BS_MAX_ITEMS ((((uint64_t)1) << 38) - 1)
+#define BS_MIN_DOMAIN_BITS 4u
+
+/* Human-readable name of a status code (static storage). */
+const char *bs_status_string(bs_status status);
+
+/* The hipError_t value behind the most recent BS_EHIP on this thread (0 if none). */
+int32_t bs_last_hip_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+uint32_t bs_version(void);
+
+/* k = max(ceil(log2 n), 4): the cipher runs on [0, 2^k) (Sec. 4 padding). */
+uint32_t bs_domain_bits(uint64_t n);
+
+/* Writes keys[r] = low 32 bits of the r-th SplitMix64 output from `seed`,
+ * r < rounds (host memory).  Exposed so callers can see the key schedule. */
+bs_status bs_round_keys(uint64_t seed, uint32_t rounds, uint32_t *keys);
+
+/*
+ * Workspace needed by one call: a 256-byte header plus one 8-byte status word
+ * per tile of the padded domain, plus (batched) per-segment tables.
+ *   single call : bs_workspace_bytes(n, 0, elem_bytes)
+ *   batched call: bs_workspace_bytes(total_items, num_segments, elem_bytes),
+ *                 total_items = offsets[num_segments].
+ * The figure is an upper bound for every launch configuration.
+ */
+size_t bs_workspace_bytes(uint64_t items, uint32_t num_segments, uint32_t elem_bytes);
+
+/*
+ * Prepares caller-owned workspace memory for first use: zero-fills it and
+ * records its capacity, asynchronously on `stream`.  A workspace must be
+ * initialised once (or zero-filled by the caller) before its first use; the
+ * library keeps it consistent afterwards.  Two calls whose executions overlap
+ * in time must not share a workspace.
+ */
+bs_status bs_workspace_init(void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Reads and clears the workspace's sticky device-side error word.  Blocks
+ * until `stream` has drained.  Returns BS_OK, BS_ETIMEOUT or BS_EDEVICE.
+ * workspace == NULL inspects the library's own workspace for (device, stream).
+ */
+bs_status bs_workspace_error(void *workspace, void *stream);
+
+/*
+ * bs_shuffle -- one bijective shuffle (Algorithm 1, fused in a single pass).
+ *
+ *   in, out     device buffers of n records of elem_bytes bytes each; they
+ *               must not overlap (BS_EALIAS) and must be aligned to
+ *               elem_bytes (BS_EELEM).  Records are moved as raw bytes, so
+ *               any payload type is bit-exact.
+ *   n           number of records, 0 <= n <= BS_MAX_ITEMS; n = 0 is a no-op.
+ *   elem_bytes  1, 2, 4, 8 or 16.
+ *   seed        any 64-bit value; selects the round keys.
+ *   rounds      0..64.  0 gives the identity permutation (out = in).
+ *   workspace   device memory of workspace_bytes >= bs_workspace_bytes(n,0,eb)
+ *               prepared by bs_workspace_init, or NULL to use the library's
+ *               per-(device, stream) cache (grown with hipMalloc when needed;
+ *               returns BS_EINVAL if it would have to grow while `stream` is
+ *               being captured into a graph).
+ *   stream      hipStream_t as void*.
+ *
+ * Writes out[rank(i)] = in[f(i)] for every padded index i < 2^k with f(i) < n.
+ */
+bs_status bs_shuffle(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                     uint32_t rounds, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * bs_shuffle_batched -- many independent shuffles in one launch sequence.
+ *
+ *   offsets     device int64[num_segments + 1], offsets[0] = 0, non-decreasing;
+ *               segment s is records [offsets[s], offsets[s+1]) of in and out.
+ *   seeds       device uint64[num_segments]: the seed of each segment.
+ *   total_items offsets[num_segments] (host copy; sizes the launch).
+ *   Other arguments as for bs_shuffle; one elem_bytes and one round count
+ *   for the whole batch.
+ *
+ * Segment s of out equals bs_shuffle of segment s of in with seeds[s],
+ * byte for byte.  A malformed offsets array is detected on the device: no
+ * byte of out is written and bs_workspace_error() reports BS_EDEVICE.
+ */
+bs_status bs_shuffle_batched(const void *in, void *out, const int64_t *offsets,
+                             const uint64_t *seeds, uint32_t num_segments, uint64_t total_items,
+                             uint32_t elem_bytes, uint32_t rounds, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/*
+ * Launch configuration (never changes results).  A tile is waves x 64 x items
+ * padded indices; depth is how many tiles a workgroup keeps in flight.
+ * Compiled shapes (waves, items, depth): (4,16,2) (8,16,2) (8,16,1)
+ * (16,16,1) (16,8,1) (8,8,2) (4,16,1).  grid_mult: 0 = a persistent grid of
+ * as many workgroups as the device keeps resident, 1..64 = that many
+ * workgroups per CU, BS_GRID_ONE_PER_TILE = one workgroup per tile.
+ * bs_set_config(0, 0, 0, 0) restores the default.  Applies to later calls
+ * from every thread; returns BS_EINVAL for a shape that is not compiled.
+ */
+#define BS_GRID_ONE_PER_TILE 1000u
+bs_status bs_set_config(uint32_t waves_per_group, uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
+bs_status bs_get_config(uint32_t *waves_per_group, uint32_t *items_per_lane, uint32_t *depth,
+                        uint32_t *grid_mult);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSHUFFLE_H */

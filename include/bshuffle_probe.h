@@ -1,0 +1,43 @@
+/*
+ * bshuffle_probe.h -- measurement kernels exported by libbshuffle.so.
+ *
+ * These are not part of the shuffle.  They are the ceilings the shuffle's
+ * throughput is reported against: the paper takes a random gather as the
+ * upper bound of any GPU shuffle (Sec. 2.2, Sec. 6), and this library also
+ * measures a plain device copy and the cipher-plus-scan work alone.
+ * Pointers are device pointers on the current device; stream is a
+ * hipStream_t as void*; returns as in bshuffle.h.
+ */
+#ifndef BSHUFFLE_PROBE_H
+#define BSHUFFLE_PROBE_H
+
+#include "bshuffle.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out[0..bytes) = in[0..bytes) with 16-byte vector loads and stores.
+ * in/out 16-byte aligned, non-overlapping. */
+bs_status bs_probe_copy(const void *in, void *out, uint64_t bytes, void *stream);
+
+/* Random gather with an index array: out[j] = in[idx[j]] for j < n, records
+ * of elem_bytes (1,2,4,8,16); idx is a device uint32 array whose entries must
+ * be < n_in (checked on the device: an out-of-range index is skipped). */
+bs_status bs_probe_gather(const void *in, uint64_t n_in, void *out, const uint32_t *idx, uint64_t n,
+                          uint32_t elem_bytes, void *stream);
+
+/* The fused shuffle kernel with no payload: cipher, keep flags, wavefront
+ * and workgroup scan, decoupled look-back; nothing is read or written but
+ * the tile status words.  Same arguments and workspace rules as bs_shuffle. */
+bs_status bs_probe_cipher_scan(uint64_t n, uint64_t seed, uint32_t rounds, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/* Selects plain (0) or non-temporal (1) output stores for bs_shuffle. */
+bs_status bs_probe_set_store_mode(uint32_t nontemporal);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSHUFFLE_PROBE_H */

@@ -1,0 +1,254 @@
+"""ctypes binding of libbshuffle.so (argument marshalling only).
+
+The raw entry points keep the C names (``bs_shuffle``, ``bs_shuffle_batched``,
+...) and take integers for pointers and streams.  ``shuffle`` and
+``shuffle_batched`` wrap them for torch tensors: the tensors' device memory
+is passed straight to the library, and the work is enqueued on the tensor's
+current torch (HIP) stream.  Every step of the shuffle runs in the library's
+HIP kernels; there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_PKG)
+LIB_PATH = os.path.join(_PKG, "libbshuffle.so")
+HEADERS = [os.path.join(_ROOT, "include", h) for h in ("bshuffle.h", "bshuffle_probe.h")]
+
+BS_OK, BS_EINVAL, BS_EALIAS, BS_EELEM, BS_ENOMEM, BS_EHIP, BS_ETIMEOUT, BS_ENODEV, BS_EDEVICE = range(9)
+MAX_ROUNDS = 64
+MAX_ITEMS = (1 << 38) - 1
+DEFAULT_ROUNDS = 24  # the round count the paper recommends (Sec. 5)
+
+
+class BShuffleError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+_u32, _u64, _i32, _sz, _vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p
+
+_SIGNATURES = {
+    "bs_status_string": (ctypes.c_char_p, [_i32]),
+    "bs_last_hip_error": (_i32, []),
+    "bs_version": (_u32, []),
+    "bs_domain_bits": (_u32, [_u64]),
+    "bs_round_keys": (_i32, [_u64, _u32, _vp]),
+    "bs_workspace_bytes": (_sz, [_u64, _u32, _u32]),
+    "bs_workspace_init": (_i32, [_vp, _sz, _vp]),
+    "bs_workspace_error": (_i32, [_vp, _vp]),
+    "bs_shuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
+    "bs_shuffle_batched": (_i32, [_vp, _vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp, _sz, _vp]),
+    "bs_set_config": (_i32, [_u32, _u32, _u32, _u32]),
+    "bs_get_config": (_i32, [_vp, _vp, _vp, _vp]),
+    "bs_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
+    "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
+    "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
+    "bs_probe_set_store_mode": (_i32, [_u32]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libbshuffle.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_2106_06161_amd.build or __graft_entry__.build())"
+            )
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def declared_functions() -> list[str]:
+    """Names of every function declared in include/*.h."""
+    names = []
+    for h in HEADERS:
+        with open(h) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(bs_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def status_string(status: int) -> str:
+    return lib().bs_status_string(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != BS_OK:
+        raise BShuffleError(status, where)
+
+
+# ------------------------------------------------------------- raw ABI --
+def bs_domain_bits(n: int) -> int:
+    return int(lib().bs_domain_bits(n))
+
+
+def bs_round_keys(seed: int, rounds: int) -> list[int]:
+    buf = (ctypes.c_uint32 * max(rounds, 1))()
+    _check(lib().bs_round_keys(seed & (2**64 - 1), rounds, buf), "bs_round_keys")
+    return list(buf)[:rounds]
+
+
+def bs_workspace_bytes(items: int, num_segments: int = 0, elem_bytes: int = 4) -> int:
+    return int(lib().bs_workspace_bytes(items, num_segments, elem_bytes))
+
+
+def bs_shuffle(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_shuffle(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, workspace,
+                                workspace_bytes, stream))
+
+
+def bs_shuffle_batched(in_ptr, out_ptr, offsets_ptr, seeds_ptr, num_segments, total_items, elem_bytes, rounds,
+                       workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_shuffle_batched(in_ptr, out_ptr, offsets_ptr, seeds_ptr, num_segments, total_items,
+                                        elem_bytes, rounds, workspace, workspace_bytes, stream))
+
+
+def bs_workspace_init(workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_workspace_init(workspace, workspace_bytes, stream))
+
+
+def bs_workspace_error(workspace, stream) -> int:
+    return int(lib().bs_workspace_error(workspace, stream))
+
+
+GRID_ONE_PER_TILE = 1000
+
+
+def bs_set_config(waves: int, items: int, depth: int, grid_mult: int) -> int:
+    return int(lib().bs_set_config(waves, items, depth, grid_mult))
+
+
+def bs_get_config() -> tuple[int, int, int, int]:
+    w, i, d, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().bs_get_config(ctypes.byref(w), ctypes.byref(i), ctypes.byref(d), ctypes.byref(g)), "bs_get_config")
+    return w.value, i.value, d.value, g.value
+
+
+def bs_probe_copy(in_ptr, out_ptr, nbytes, stream) -> int:
+    return int(lib().bs_probe_copy(in_ptr, out_ptr, nbytes, stream))
+
+
+def bs_probe_gather(in_ptr, n_in, out_ptr, idx_ptr, n, elem_bytes, stream) -> int:
+    return int(lib().bs_probe_gather(in_ptr, n_in, out_ptr, idx_ptr, n, elem_bytes, stream))
+
+
+def bs_probe_cipher_scan(n, seed, rounds, workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_probe_cipher_scan(n, seed & (2**64 - 1), rounds, workspace, workspace_bytes, stream))
+
+
+def bs_probe_set_store_mode(nontemporal: int) -> int:
+    return int(lib().bs_probe_set_store_mode(nontemporal))
+
+
+# ---------------------------------------------------- torch-level API --
+def _records(x) -> tuple[int, int]:
+    """(n, elem_bytes) of a tensor permuted along dim 0."""
+    n = x.shape[0] if x.dim() else 1
+    trailing = 1
+    for d in x.shape[1:]:
+        trailing *= d
+    return n, x.element_size() * trailing
+
+
+def _stream_ptr(x, stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _require_device(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the shuffle runs only in HIP kernels)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(items: int, num_segments: int = 0, elem_bytes: int = 4) -> int:
+    return bs_workspace_bytes(items, num_segments, elem_bytes)
+
+
+def make_workspace(nbytes: int, device=None, stream=None):
+    """Allocates and initialises a caller-owned workspace tensor."""
+    import torch
+
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+    _check(bs_workspace_init(ws.data_ptr(), ws.numel(), _stream_ptr(ws, stream)), "bs_workspace_init")
+    return ws
+
+
+def shuffle(x, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, workspace=None, stream=None):
+    """Bijective shuffle of x along dim 0 (one record = x[i], raw bytes)."""
+    import torch
+
+    _require_device(x, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    _require_device(out, "out")
+    if out.shape != x.shape or out.dtype != x.dtype:
+        raise ValueError("out must match x in shape and dtype")
+    n, eb = _records(x)
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
+    with torch.cuda.device(x.device):
+        st = bs_shuffle(x.data_ptr(), out.data_ptr(), n, eb, seed, rounds, ws_ptr, ws_bytes, _stream_ptr(x, stream))
+    _check(st, "bs_shuffle")
+    return out
+
+
+def shuffle_batched(x, offsets, seeds, rounds: int = DEFAULT_ROUNDS, out=None, total_items=None, workspace=None,
+                    stream=None):
+    """Independent shuffles of the segments x[offsets[s]:offsets[s+1]] with seeds[s].
+
+    offsets: int64 GPU tensor of S+1 entries; seeds: int64 (bit pattern of the
+    uint64 seed) GPU tensor of S entries.  total_items defaults to x.shape[0]."""
+    import torch
+
+    _require_device(x, "x")
+    _require_device(offsets, "offsets")
+    _require_device(seeds, "seeds")
+    if offsets.dtype != torch.int64 or seeds.dtype not in (torch.int64, torch.uint64):
+        raise ValueError("offsets must be int64 and seeds int64/uint64")
+    s = seeds.numel()
+    if offsets.numel() != s + 1:
+        raise ValueError("offsets needs num_segments + 1 entries")
+    if out is None:
+        out = torch.empty_like(x)
+    _require_device(out, "out")
+    n, eb = _records(x)
+    total = n if total_items is None else int(total_items)
+    if total > n:
+        raise ValueError("total_items exceeds x")
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
+    with torch.cuda.device(x.device):
+        st = bs_shuffle_batched(x.data_ptr(), out.data_ptr(), offsets.data_ptr(), seeds.data_ptr(), s, total, eb,
+                                rounds, ws_ptr, ws_bytes, _stream_ptr(x, stream))
+    _check(st, "bs_shuffle_batched")
+    return out
+
+
+def workspace_error(workspace=None, stream=None, device=None) -> int:
+    """Drains the stream and returns (and clears) the workspace's device-side error status."""
+    import torch
+
+    dev = workspace.device if workspace is not None else torch.device(device or "cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    with torch.cuda.device(dev):
+        return bs_workspace_error(workspace.data_ptr() if workspace is not None else None, sp)

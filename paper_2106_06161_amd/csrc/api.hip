@@ -1,0 +1,378 @@
+// C ABI of libbshuffle.so: argument checks, the key schedule, workspace
+// management and kernel dispatch.  Declarations and contracts are in
+// include/bshuffle.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "bshuffle.h"
+#include "bshuffle_probe.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+bs_status hip_fail(hipError_t e) {
+  g_last_hip_error = static_cast<int32_t>(e);
+  return BS_EHIP;
+}
+
+// The smallest tile any launch configuration uses: sizes the status array.
+constexpr uint64_t kMinTile = 2048;  // indices; no compiled shape has a smaller tile
+constexpr size_t kHeaderBytes = sizeof(bsd::WorkspaceHeader);
+
+std::mutex g_mu;
+bsd::LaunchConfig g_default_cfg = {16, 16, 1, 0};
+bsd::LaunchConfig g_cfg = g_default_cfg;
+bool g_nontemporal_store = false;
+
+struct CacheEntry {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::map<std::pair<int, hipStream_t>, CacheEntry> g_cache;
+std::map<int, uint32_t> g_num_cus;
+
+uint32_t ceil_log2(uint64_t n) {
+  uint32_t k = 0;
+  while (k < 64 && (uint64_t(1) << k) < n) ++k;
+  return k;
+}
+
+uint64_t splitmix64_step(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+bool valid_elem_bytes(uint32_t eb) { return eb == 1 || eb == 2 || eb == 4 || eb == 8 || eb == 16; }
+
+uint64_t single_capacity(uint64_t n) {
+  const uint32_t k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
+  return ((uint64_t(1) << k) + kMinTile - 1) / kMinTile;
+}
+
+// Upper bound on the total tiles of a batch: every non-empty segment pads to
+// at most max(16, 2n_s - 1) indices, and rounds its tile count up by one.
+uint64_t batch_capacity(uint64_t items, uint32_t segments) {
+  return (2 * items + 16ull * segments) / kMinTile + segments + 1;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct BatchLayout {
+  size_t status, segs, keys, tile_segment, total;
+  uint64_t capacity;
+};
+
+BatchLayout batch_layout(uint64_t items, uint32_t segments) {
+  BatchLayout l;
+  l.capacity = batch_capacity(items, segments);
+  l.status = kHeaderBytes;
+  l.segs = align256(l.status + l.capacity * 8);
+  l.keys = align256(l.segs + size_t(segments) * sizeof(bsd::SegmentInfo));
+  l.tile_segment = align256(l.keys + size_t(segments) * BS_MAX_ROUNDS * 4);
+  l.total = align256(l.tile_segment + l.capacity * 4);
+  return l;
+}
+
+bs_status device_cus(int dev, uint32_t* cus) {
+  auto it = g_num_cus.find(dev);
+  if (it != g_num_cus.end()) {
+    *cus = it->second;
+    return BS_OK;
+  }
+  int v = 0;
+  hipError_t e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e);
+  g_num_cus[dev] = uint32_t(v);
+  *cus = uint32_t(v);
+  return BS_OK;
+}
+
+// Resolves the workspace for a call: the caller's, or the library's cache
+// entry for (device, stream), grown when too small.
+bs_status resolve_workspace(void* user, size_t user_bytes, size_t need, hipStream_t stream, void** ws) {
+  if (user) {
+    if (user_bytes < need) return BS_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(user) % 256 != 0) return BS_EINVAL;
+    *ws = user;
+    return BS_OK;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  CacheEntry& c = g_cache[{dev, stream}];
+  if (c.bytes >= need) {
+    *ws = c.ptr;
+    return BS_OK;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  e = hipStreamIsCapturing(stream, &cap);
+  if (e != hipSuccess) return hip_fail(e);
+  if (cap != hipStreamCaptureStatusNone) return BS_EINVAL;  // cannot allocate during capture
+  size_t bytes = std::max(need, size_t(1) << 20);
+  if (c.ptr) {
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipFree(c.ptr);
+    c.ptr = nullptr;
+    c.bytes = 0;
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  void* p = nullptr;
+  e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? BS_ENOMEM : hip_fail(e);
+  e = bsd::launch_workspace_init(p, bytes, stream);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_fail(e);
+  }
+  c.ptr = p;
+  c.bytes = bytes;
+  *ws = p;
+  return BS_OK;
+}
+
+bool ranges_overlap(const void* a, const void* b, uint64_t bytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bs_status_string(bs_status s) {
+  switch (s) {
+    case BS_OK: return "BS_OK: success";
+    case BS_EINVAL: return "BS_EINVAL: invalid argument";
+    case BS_EALIAS: return "BS_EALIAS: input and output overlap";
+    case BS_EELEM: return "BS_EELEM: element size must be 1, 2, 4, 8 or 16 bytes and pointers aligned to it";
+    case BS_ENOMEM: return "BS_ENOMEM: workspace too small or allocation failed";
+    case BS_EHIP: return "BS_EHIP: HIP runtime error";
+    case BS_ETIMEOUT: return "BS_ETIMEOUT: look-back wait exceeded its spin limit";
+    case BS_ENODEV: return "BS_ENODEV: no HIP device";
+    case BS_EDEVICE: return "BS_EDEVICE: batch rejected on the device (bad offsets or too many tiles)";
+    default: return "unknown bs_status";
+  }
+}
+
+int32_t bs_last_hip_error(void) { return g_last_hip_error; }
+
+uint32_t bs_version(void) { return 100; }
+
+uint32_t bs_domain_bits(uint64_t n) { return std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS); }
+
+bs_status bs_round_keys(uint64_t seed, uint32_t rounds, uint32_t* keys) {
+  if (rounds > BS_MAX_ROUNDS || (rounds && !keys)) return BS_EINVAL;
+  uint64_t st = seed;
+  for (uint32_t r = 0; r < rounds; ++r) keys[r] = uint32_t(splitmix64_step(st));
+  return BS_OK;
+}
+
+size_t bs_workspace_bytes(uint64_t items, uint32_t num_segments, uint32_t elem_bytes) {
+  (void)elem_bytes;
+  if (num_segments == 0) return align256(kHeaderBytes + single_capacity(items) * 8);
+  return batch_layout(items, num_segments).total;
+}
+
+bs_status bs_workspace_init(void* workspace, size_t workspace_bytes, void* stream) {
+  if (!workspace || workspace_bytes < kHeaderBytes) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return BS_EINVAL;
+  hipError_t e = bsd::launch_workspace_init(workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+bs_status bs_workspace_error(void* workspace, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = workspace;
+  if (!ws) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find({dev, s});
+    if (it == g_cache.end() || !it->second.ptr) return BS_OK;
+    ws = it->second.ptr;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t err = 0;
+  auto* hdr = static_cast<bsd::WorkspaceHeader*>(ws);
+  e = hipMemcpy(&err, &hdr->error, sizeof(err), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e);
+  if (err) {
+    const uint32_t zero = 0;
+    e = hipMemcpy(&hdr->error, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (err & bsd::kErrTimeout) return BS_ETIMEOUT;
+  if (err & bsd::kErrBadBatch) return BS_EDEVICE;
+  return BS_OK;
+}
+
+bs_status bs_set_config(uint32_t waves, uint32_t items, uint32_t depth, uint32_t grid_mult) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (waves == 0 && items == 0 && depth == 0 && grid_mult == 0) {
+    g_cfg = g_default_cfg;
+    return BS_OK;
+  }
+  bsd::LaunchConfig c = {waves, items, depth, grid_mult};
+  if (!bsd::config_supported(c) || (grid_mult > 64 && grid_mult != bsd::kGridOnePerTile)) return BS_EINVAL;
+  g_cfg = c;
+  return BS_OK;
+}
+
+bs_status bs_get_config(uint32_t* waves, uint32_t* items, uint32_t* depth, uint32_t* grid_mult) {
+  if (!waves || !items || !depth || !grid_mult) return BS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  *waves = g_cfg.waves;
+  *items = g_cfg.items;
+  *depth = g_cfg.depth;
+  *grid_mult = g_cfg.grid_mult;
+  return BS_OK;
+}
+
+bs_status bs_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t rounds,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t k = bs_domain_bits(n);
+  bsd::SingleArgs a = {};
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  a.n = n;
+  a.domain = uint64_t(1) << k;
+  a.cs.w = k / 2;
+  a.cs.r = k - a.cs.w;
+  a.cs.wmask = (1u << a.cs.w) - 1u;
+  a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
+  a.rounds = rounds;
+  bs_round_keys(seed, rounds, a.key);
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  const bsd::LaunchConfig cfg = g_cfg;
+  const bool wide = k > 32;
+  const uint64_t tile = wide ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;
+  a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
+  const size_t need = bs_workspace_bytes(n, 0, elem_bytes);
+  void* ws = nullptr;
+  bs_status st = resolve_workspace(workspace, workspace_bytes, need, s, &ws);
+  if (st != BS_OK) return st;
+  a.hdr = static_cast<bsd::WorkspaceHeader*>(ws);
+  a.status = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(ws) + kHeaderBytes);
+  a.capacity = uint32_t(single_capacity(n));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t cus = 0;
+  st = device_cus(dev, &cus);
+  if (st != BS_OK) return st;
+  e = bsd::launch_single(a, elem_bytes, g_nontemporal_store, cfg, cus, s);
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, const uint64_t* seeds,
+                             uint32_t num_segments, uint64_t total_items, uint32_t elem_bytes, uint32_t rounds,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || total_items > BS_MAX_ITEMS) return BS_EINVAL;
+  if (num_segments == 0 || total_items == 0) return BS_OK;
+  if (!in || !out || !offsets || !seeds) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (ranges_overlap(in, out, total_items * elem_bytes)) return BS_EALIAS;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const BatchLayout lay = batch_layout(total_items, num_segments);
+  if (lay.capacity > 0xFFFFFFFFull) return BS_EINVAL;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  const bsd::LaunchConfig cfg = g_cfg;
+  void* ws = nullptr;
+  bs_status st = resolve_workspace(workspace, workspace_bytes, lay.total, s, &ws);
+  if (st != BS_OK) return st;
+  uint8_t* base = static_cast<uint8_t*>(ws);
+  bsd::BatchArgs a = {};
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  a.offsets = offsets;
+  a.seeds = seeds;
+  a.num_segments = num_segments;
+  a.rounds = rounds;
+  a.capacity = uint32_t(lay.capacity);
+  a.tile = 64u * cfg.waves * cfg.items;
+  a.nontemporal = g_nontemporal_store ? 1u : 0u;
+  a.hdr = reinterpret_cast<bsd::WorkspaceHeader*>(base);
+  a.status = reinterpret_cast<uint64_t*>(base + lay.status);
+  a.segs = reinterpret_cast<bsd::SegmentInfo*>(base + lay.segs);
+  a.keys = reinterpret_cast<uint32_t*>(base + lay.keys);
+  a.tile_segment = reinterpret_cast<uint32_t*>(base + lay.tile_segment);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t cus = 0;
+  st = device_cus(dev, &cus);
+  if (st != BS_OK) return st;
+  e = bsd::launch_batched(a, elem_bytes, cfg, cus, s);
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- probe entry points --
+extern "C" bs_status bs_probe_set_store_mode(uint32_t nontemporal) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_nontemporal_store = nontemporal != 0;
+  return BS_OK;
+}
+
+extern "C" bs_status bs_probe_cipher_scan(uint64_t n, uint64_t seed, uint32_t rounds, void* workspace,
+                                          size_t workspace_bytes, void* stream) {
+  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t k = bs_domain_bits(n);
+  bsd::SingleArgs a = {};
+  a.n = n;
+  a.domain = uint64_t(1) << k;
+  a.cs.w = k / 2;
+  a.cs.r = k - a.cs.w;
+  a.cs.wmask = (1u << a.cs.w) - 1u;
+  a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
+  a.rounds = rounds;
+  bs_round_keys(seed, rounds, a.key);
+  std::lock_guard<std::mutex> lock(g_mu);
+  const bsd::LaunchConfig cfg = g_cfg;
+  const uint64_t tile = k > 32 ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;
+  a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
+  void* ws = nullptr;
+  bs_status st = resolve_workspace(workspace, workspace_bytes, bs_workspace_bytes(n, 0, 4), s, &ws);
+  if (st != BS_OK) return st;
+  a.hdr = static_cast<bsd::WorkspaceHeader*>(ws);
+  a.status = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(ws) + kHeaderBytes);
+  a.capacity = uint32_t(single_capacity(n));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t cus = 0;
+  st = device_cus(dev, &cus);
+  if (st != BS_OK) return st;
+  e = bsd::launch_single(a, 0, false, cfg, cus, s);
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}

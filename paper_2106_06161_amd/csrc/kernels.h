@@ -1,0 +1,92 @@
+// Kernel argument blocks and host-side launchers shared by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tile_scan.h"
+#include "vphilox_round.h"
+
+namespace bsd {
+
+constexpr uint32_t kMaxRounds = 64;
+
+// One bijective shuffle (Algorithm 1) over a padded domain of 2^k indices.
+struct SingleArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t n;          // items kept (input length)
+  uint64_t domain;     // 2^k
+  CipherShape cs;
+  uint32_t rounds;
+  uint32_t num_tiles;  // ceil(domain / tile)
+  uint32_t capacity;   // status words the workspace holds
+  uint32_t nontemporal;  // 1: output stores bypass cache retention
+  WorkspaceHeader* hdr;
+  uint64_t* status;
+  uint32_t key[kMaxRounds];
+};
+
+// Per-segment record written by the batch preparation kernel.
+struct SegmentInfo {
+  uint64_t first;       // first record of the segment in in/out
+  uint64_t n;           // records in the segment
+  uint32_t first_tile;  // index of the segment's first tile (and status word)
+  uint32_t k;           // domain bits of the segment
+};
+
+struct BatchArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  const int64_t* offsets;  // device, num_segments + 1
+  const uint64_t* seeds;   // device, num_segments
+  uint32_t num_segments;
+  uint32_t rounds;
+  uint32_t capacity;        // status words the workspace holds (= max tiles)
+  uint32_t tile;            // indices per tile of the launch configuration
+  uint32_t nontemporal;     // 1: output stores bypass cache retention
+  WorkspaceHeader* hdr;
+  uint64_t* status;
+  SegmentInfo* segs;        // num_segments records
+  uint32_t* keys;           // num_segments * rounds round keys
+  uint32_t* tile_segment;   // capacity entries: segment owning each tile
+};
+
+struct LaunchConfig {
+  uint32_t waves;      // wavefronts per workgroup
+  uint32_t items;      // indices per lane per tile
+  uint32_t depth;      // tiles a workgroup keeps in flight (1 or 2)
+  uint32_t grid_mult;  // 0: as many workgroups as stay resident (persistent);
+                       // 1..64: that many per CU; kGridOnePerTile: one per tile
+};
+constexpr uint32_t kGridOnePerTile = 1000;
+
+hipError_t launch_single(const SingleArgs& a, uint32_t elem_bytes, bool nontemporal, const LaunchConfig& cfg,
+                         uint32_t num_cus, hipStream_t stream);
+hipError_t launch_batched(const BatchArgs& a, uint32_t elem_bytes, const LaunchConfig& cfg, uint32_t num_cus,
+                          hipStream_t stream);
+hipError_t launch_workspace_init(void* ws, size_t bytes, hipStream_t stream);
+
+bool config_supported(const LaunchConfig& cfg);
+
+using SingleFn = void (*)(SingleArgs);
+using BatchFn = void (*)(BatchArgs);
+
+// Per-element-size kernel selection (one translation unit each).
+// Tile shapes that are compiled: (waves per workgroup, indices per lane, depth).
+#define BSD_FOR_EACH_SHAPE(X) X(4, 16, 2) X(8, 16, 2) X(8, 16, 1) X(16, 16, 1) X(16, 8, 1) X(8, 8, 2) X(4, 16, 1)
+// Shape used when the index space needs 64 bits (k > 32).
+constexpr uint32_t kWideWaves = 8, kWideItems = 16;
+
+#define BSD_DECLARE_PICK(EB)                                                    \
+  SingleFn pick_single_##EB(bool odd, bool wide, const LaunchConfig& c);        \
+  BatchFn pick_batch_##EB(const LaunchConfig& c);
+BSD_DECLARE_PICK(0)
+BSD_DECLARE_PICK(1)
+BSD_DECLARE_PICK(2)
+BSD_DECLARE_PICK(4)
+BSD_DECLARE_PICK(8)
+BSD_DECLARE_PICK(16)
+#undef BSD_DECLARE_PICK
+
+}  // namespace bsd

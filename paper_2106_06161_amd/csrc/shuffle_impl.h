@@ -1,0 +1,405 @@
+// Fused single-pass bijective shuffle kernels for gfx950 (Algorithm 1, Sec. 4,
+// in the fully fused form of Sec. 6's "Bijective2": one read and one write per
+// kept item, no intermediate array in HBM).
+//
+// A workgroup of WAVES wavefronts owns a tile of 64*WAVES*ITEMS consecutive
+// padded indices.  Wavefront w, lane l, item j handles index
+//     tile*TILE + w*64*ITEMS + j*64 + l,
+// so every item step of a wavefront covers 64 consecutive indices and one
+// __ballot of the keep flags gives each lane its rank among them (mbcnt).
+// Per tile:
+//   1. cipher: ITEMS VariablePhilox evaluations per lane, interleaved for ILP;
+//   2. keep = index < 2^k and f(index) < n; ballot -> wave-local ranks;
+//   3. the random gathers in[f(i)] are issued at once, so their latency
+//      overlaps the scan below;
+//   4. wave counts -> LDS -> tile total; wavefront 0 runs the decoupled
+//      look-back for the tile's exclusive prefix;
+//   5. kept items are stored at out[prefix + rank]: each item step of a
+//      wavefront writes one contiguous run of the output.
+// Tiles are handed out by an atomic ticket in launch order, so a tile only
+// ever waits on tiles already owned by running workgroups.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace bsd {
+
+// ------------------------------------------------------------ payloads --
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int EB> struct Payload;
+template <> struct Payload<0> { using T = uint32_t; };  // no payload (cipher + scan probe)
+template <> struct Payload<1> { using T = uint8_t; };
+template <> struct Payload<2> { using T = uint16_t; };
+template <> struct Payload<4> { using T = uint32_t; };
+template <> struct Payload<8> { using T = u32x2; };
+template <> struct Payload<16> { using T = u32x4; };
+
+template <int EB>
+__device__ __forceinline__ typename Payload<EB>::T load_record(const uint8_t* __restrict__ base, uint64_t idx) {
+  using T = typename Payload<EB>::T;
+  return *reinterpret_cast<const T*>(base + idx * uint64_t(EB));
+}
+
+template <int EB, bool NT>
+__device__ __forceinline__ void store_record(uint8_t* __restrict__ base, uint64_t idx, typename Payload<EB>::T v) {
+  using T = typename Payload<EB>::T;
+  T* p = reinterpret_cast<T*>(base + idx * uint64_t(EB));
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// ------------------------------------------------------ workgroup state --
+template <int WAVES>
+struct TileLds {
+  uint32_t ticket;
+  uint32_t next_ticket;
+  uint32_t gen;
+  uint32_t last;
+  uint32_t limit;
+  uint32_t wave_count[WAVES];
+  uint64_t tile_exclusive;
+};
+
+// Starts a workgroup: reads the launch generation and takes the first ticket.
+// Plain (relaxed) atomics: the header was last written by an earlier kernel,
+// and kernel boundaries already make those writes visible; an acquire here
+// would invalidate the XCD's L2 once per workgroup.
+template <int WAVES>
+__device__ __forceinline__ void group_begin(WorkspaceHeader* hdr, TileLds<WAVES>& lds) {
+  if (threadIdx.x == 0) {
+    lds.gen = __hip_atomic_load(&hdr->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lds.limit = __hip_atomic_load(&hdr->batch_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lds.ticket = atomicAdd(&hdr->ticket, 1u);
+  }
+  __syncthreads();
+}
+
+// Ends a workgroup.  The last one to finish resets the ticket and the done
+// counter and advances the generation; when the 24-bit tag wraps it first
+// clears every status word so no stale word can carry a future tag.
+// Ordering without fences: a workgroup's last ticket fetch returned its value
+// before the workgroup got here, and the wait below retires its status stores
+// before it counts itself done; the done counter's modification order then
+// puts every other workgroup's traffic before the last one's reset.
+template <int WAVES>
+__device__ __forceinline__ void group_end(WorkspaceHeader* hdr, uint64_t* status, uint32_t capacity,
+                                          uint32_t gen, TileLds<WAVES>& lds) {
+  __builtin_amdgcn_s_waitcnt(0);
+  if (threadIdx.x == 0) {
+    const uint32_t d = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lds.last = (d == gridDim.x - 1) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (lds.last) {
+    const uint32_t next_gen = gen + 1;
+    if ((next_gen & kTagMask) == 0) {
+      const uint32_t cap = max(capacity, hdr->capacity);
+      for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) atomic_store_agent(status + i, 0);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&hdr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&hdr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&hdr->gen, next_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ------------------------------------------------------------- tile phases --
+// A tile is processed in three phases so that a persistent workgroup can keep
+// one tile's gathers in flight while it runs the next tile's cipher:
+//   gather: cipher, keep flags, wave-local ranks, random loads issued;
+//   scan:   workgroup scan of the wave counts and the decoupled look-back;
+//   store:  kept records written at prefix + rank.
+constexpr uint32_t kDropped = 0xFFFFFFFFu;
+
+template <int EB, int ITEMS>
+struct PendingTile {
+  typename Payload<EB>::T val[ITEMS];  // gathered records (loads may be in flight)
+  uint32_t rank[ITEMS];                // wave-local output rank, kDropped if not kept
+  uint32_t wave_count;                 // kept indices of this wave (uniform)
+};
+
+template <int EB, bool ODD, int WAVES, int ITEMS, bool WIDE>
+__device__ __forceinline__ void tile_gather(PendingTile<EB, ITEMS>& t, const uint8_t* __restrict__ in, uint64_t n,
+                                            uint64_t domain, const CipherShape cs, uint32_t rounds,
+                                            const uint32_t* __restrict__ keys, uint64_t tile_in_segment) {
+  using Idx = std::conditional_t<WIDE, uint64_t, uint32_t>;
+  constexpr uint32_t kTile = 64u * WAVES * ITEMS;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = threadIdx.x >> 6;
+  const Idx base = Idx(tile_in_segment) * Idx(kTile) + Idx(wave * (64u * ITEMS) + lane);
+
+  uint32_t L[ITEMS], R[ITEMS];
+  const uint32_t wmask24 = cs.wmask & 0xFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const Idx x = base + Idx(j * 64);
+    L[j] = uint32_t(x >> cs.r) & wmask24;
+    R[j] = uint32_t(x);
+  }
+  vp_encrypt<ODD, ITEMS>(L, R, cs, rounds, keys);
+
+  uint32_t wave_count = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const Idx x = base + Idx(j * 64);
+    const Idx y = (Idx(L[j]) << cs.r) | Idx(R[j] & cs.rmask);
+    const bool keep = (uint64_t(x) < domain) && (uint64_t(y) < n);
+    const uint64_t m = __ballot(keep);
+    const uint32_t below =
+        __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    t.rank[j] = keep ? wave_count + below : kDropped;
+    if constexpr (EB > 0) {
+      if (keep) t.val[j] = load_record<EB>(in, uint64_t(y));
+    }
+    wave_count += uint32_t(__builtin_popcountll(m));
+  }
+  t.wave_count = wave_count;
+}
+
+// Returns this wave's output base: kept indices before the tile (look-back)
+// plus those of lower waves in the tile.  Takes the workgroup's next ticket.
+template <int WAVES>
+__device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* status, uint32_t status_first,
+                                              uint32_t status_idx, uint32_t tag, WorkspaceHeader* hdr,
+                                              TileLds<WAVES>& lds) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = threadIdx.x >> 6;
+  if (lane == 0) lds.wave_count[wave] = wave_count;
+  __syncthreads();
+  uint32_t wave_exclusive = 0, tile_total = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    const uint32_t c = lds.wave_count[w];
+    wave_exclusive += (uint32_t(w) < wave) ? c : 0u;
+    tile_total += c;
+  }
+  constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
+  if (wave == kTicketWave && lane == 0) lds.next_ticket = atomicAdd(&hdr->ticket, 1u);
+  if (wave == 0) {
+    const uint64_t ex =
+        lookback_exclusive_prefix(status, status_first, status_idx, tag, uint64_t(tile_total), &hdr->error);
+    if (lane == 0) lds.tile_exclusive = ex;
+  }
+  __syncthreads();
+  return lds.tile_exclusive + wave_exclusive;
+}
+
+// Positions are < n by construction; the bound check only keeps a timed-out
+// look-back from writing outside the buffer.
+template <int EB, int ITEMS>
+__device__ __forceinline__ void tile_store(const PendingTile<EB, ITEMS>& t, uint8_t* __restrict__ out, uint64_t n,
+                                           uint64_t prefix, bool nontemporal) {
+  if constexpr (EB > 0) {
+    if (nontemporal) {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint64_t pos = prefix + t.rank[j];
+        if (t.rank[j] != kDropped && pos < n) store_record<EB, true>(out, pos, t.val[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const uint64_t pos = prefix + t.rank[j];
+        if (t.rank[j] != kDropped && pos < n) store_record<EB, false>(out, pos, t.val[j]);
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------- single kernel --
+// Persistent loop over tickets.  DEPTH 2 keeps two tiles in flight: the
+// gather phase of the next tile (cipher + loads issued) runs while the loads
+// of the current tile are outstanding, then the current tile is stored.
+// DEPTH 1 finishes each tile before starting the next (fewer registers).
+template <int EB, bool ODD, int WAVES, int ITEMS, int DEPTH, bool WIDE>
+__global__ __launch_bounds__(WAVES * 64) void shuffle_single_kernel(const SingleArgs a) {
+  __shared__ TileLds<WAVES> lds;
+  group_begin(a.hdr, lds);
+  const uint32_t gen = lds.gen;
+  const uint32_t tag = gen & kTagMask;
+  const bool nt = a.nontemporal != 0;
+  uint32_t tile = lds.ticket;
+  if constexpr (DEPTH == 1) {
+    PendingTile<EB, ITEMS> cur;
+    while (tile < a.num_tiles) {
+      tile_gather<EB, ODD, WAVES, ITEMS, WIDE>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile);
+      const uint64_t prefix = tile_scan(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds);
+      tile_store(cur, a.out, a.n, prefix, nt);
+      tile = lds.next_ticket;
+    }
+  } else {
+    PendingTile<EB, ITEMS> cur, nxt;
+    uint64_t cur_prefix = 0;
+    if (tile < a.num_tiles) {
+      tile_gather<EB, ODD, WAVES, ITEMS, WIDE>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile);
+      cur_prefix = tile_scan(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds);
+    }
+    while (tile < a.num_tiles) {
+      const uint32_t next = lds.next_ticket;
+      const bool more = next < a.num_tiles;
+      if (more) tile_gather<EB, ODD, WAVES, ITEMS, WIDE>(nxt, a.in, a.n, a.domain, a.cs, a.rounds, a.key, next);
+      tile_store(cur, a.out, a.n, cur_prefix, nt);
+      if (more) {
+        cur_prefix = tile_scan(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds);
+        cur = nxt;
+      }
+      tile = next;
+    }
+  }
+  group_end(a.hdr, a.status, a.capacity, gen, lds);
+}
+
+// ------------------------------------------------------- batched kernels --
+__device__ __forceinline__ uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t domain_bits_dev(uint64_t n) {
+  uint32_t k = (n <= 1) ? 0u : 64u - uint32_t(__builtin_clzll(n - 1));
+  return k < 4u ? 4u : k;
+}
+
+// Uniform view of one tile of a batch: its segment's slice and cipher.
+struct BatchTile {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t n;
+  uint64_t domain;
+  const uint32_t* keys;
+  CipherShape cs;
+  uint32_t first_tile;
+  uint32_t tile_in_segment;
+  bool odd;
+};
+
+template <int EB>
+__device__ __forceinline__ BatchTile batch_tile(const BatchArgs& a, uint32_t tile) {
+  BatchTile b;
+  const uint32_t s = __builtin_amdgcn_readfirstlane(a.tile_segment[tile]);
+  const SegmentInfo si = a.segs[s];
+  const uint32_t k = __builtin_amdgcn_readfirstlane(si.k);
+  b.cs.w = k >> 1;
+  b.cs.r = k - b.cs.w;
+  b.cs.wmask = (1u << b.cs.w) - 1u;
+  b.cs.rmask = (1u << b.cs.r) - 1u;
+  b.keys = a.keys + uint64_t(s) * a.rounds;
+  b.in = a.in + si.first * uint64_t(EB);
+  b.out = a.out + si.first * uint64_t(EB);
+  b.n = si.n;
+  b.domain = uint64_t(1) << k;
+  b.first_tile = si.first_tile;
+  b.tile_in_segment = tile - si.first_tile;
+  b.odd = (k & 1u) != 0;
+  return b;
+}
+
+template <int EB, int WAVES, int ITEMS>
+__device__ __forceinline__ void batch_gather(PendingTile<EB, ITEMS>& t, const BatchTile& b, uint32_t rounds) {
+  if (b.odd)
+    tile_gather<EB, true, WAVES, ITEMS, false>(t, b.in, b.n, b.domain, b.cs, rounds, b.keys, b.tile_in_segment);
+  else
+    tile_gather<EB, false, WAVES, ITEMS, false>(t, b.in, b.n, b.domain, b.cs, rounds, b.keys, b.tile_in_segment);
+}
+
+template <int EB, int WAVES, int ITEMS, int DEPTH>
+__global__ __launch_bounds__(WAVES * 64) void shuffle_batched_kernel(const BatchArgs a) {
+  __shared__ TileLds<WAVES> lds;
+  group_begin(a.hdr, lds);
+  const uint32_t gen = lds.gen;
+  const uint32_t tag = gen & kTagMask;
+  const uint32_t limit = lds.limit;
+  const bool nt = a.nontemporal != 0;
+  uint32_t tile = lds.ticket;
+  if constexpr (DEPTH == 1) {
+    PendingTile<EB, ITEMS> cur;
+    while (tile < limit) {
+      const BatchTile b = batch_tile<EB>(a, tile);
+      batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
+      const uint64_t prefix = tile_scan(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
+      tile_store(cur, b.out, b.n, prefix, nt);
+      tile = lds.next_ticket;
+    }
+  } else {
+    PendingTile<EB, ITEMS> cur, nxt;
+    uint64_t cur_prefix = 0;
+    uint8_t* cur_out = nullptr;
+    uint64_t cur_n = 0;
+    if (tile < limit) {
+      const BatchTile b = batch_tile<EB>(a, tile);
+      batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
+      cur_prefix = tile_scan(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
+      cur_out = b.out;
+      cur_n = b.n;
+    }
+    while (tile < limit) {
+      const uint32_t next = lds.next_ticket;
+      const bool more = next < limit;
+      BatchTile b;
+      if (more) {
+        b = batch_tile<EB>(a, next);
+        batch_gather<EB, WAVES, ITEMS>(nxt, b, a.rounds);
+      }
+      tile_store(cur, cur_out, cur_n, cur_prefix, nt);
+      if (more) {
+        cur_prefix = tile_scan(nxt.wave_count, a.status, b.first_tile, next, tag, a.hdr, lds);
+        cur = nxt;
+        cur_out = b.out;
+        cur_n = b.n;
+      }
+      tile = next;
+    }
+  }
+  group_end(a.hdr, a.status, a.capacity, gen, lds);
+}
+
+// ------------------------------------------------------------ dispatch --
+// Kernels are instantiated per element size in separate translation units
+// (inst_eb*.hip) so the build compiles them in parallel.  Supported shapes
+// (waves, items, depth) are listed once in BSD_FOR_EACH_SHAPE (kernels.h).
+template <int EB, bool ODD, bool WIDE>
+SingleFn pick_single_shape(const LaunchConfig& c) {
+  if constexpr (WIDE) {
+    return &shuffle_single_kernel<EB, ODD, 8, 16, 1, true>;
+  } else {
+#define BSD_PICK(W, I, D) \
+  if (c.waves == W && c.items == I && c.depth == D) return &shuffle_single_kernel<EB, ODD, W, I, D, false>;
+    BSD_FOR_EACH_SHAPE(BSD_PICK)
+#undef BSD_PICK
+    return nullptr;
+  }
+}
+
+template <int EB>
+SingleFn pick_single_eb(bool odd, bool wide, const LaunchConfig& c) {
+  if (wide) return odd ? pick_single_shape<EB, true, true>(c) : pick_single_shape<EB, false, true>(c);
+  return odd ? pick_single_shape<EB, true, false>(c) : pick_single_shape<EB, false, false>(c);
+}
+
+template <int EB>
+BatchFn pick_batch_eb(const LaunchConfig& c) {
+#define BSD_PICK(W, I, D) \
+  if (c.waves == W && c.items == I && c.depth == D) return &shuffle_batched_kernel<EB, W, I, D>;
+  BSD_FOR_EACH_SHAPE(BSD_PICK)
+#undef BSD_PICK
+  return nullptr;
+}
+
+}  // namespace bsd

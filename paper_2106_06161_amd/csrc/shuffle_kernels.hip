@@ -1,0 +1,195 @@
+// Batch preparation kernels, workspace initialisation and the host-side
+// launchers for the fused shuffle kernels (templates in shuffle_impl.h,
+// instantiated per element size in inst_eb*.hip).
+#include <map>
+#include <utility>
+
+#include "shuffle_impl.h"
+
+namespace bsd {
+
+// One workgroup of 1024 threads: per-segment sizes, domain bits, round keys,
+// and the exclusive scan of tile counts.  Rejects the whole batch (no tile is
+// run) if the offsets are malformed, a segment needs more than 32 index bits,
+// or the tiles exceed the workspace.
+constexpr uint32_t kPrepThreads = 1024;
+__global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(const BatchArgs a) {
+  __shared__ uint32_t warp_sums[kPrepThreads / 64];
+  __shared__ uint32_t carry;
+  __shared__ uint32_t bad;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) {
+    carry = 0;
+    bad = (a.offsets[0] != 0) ? 1u : 0u;
+  }
+  __syncthreads();
+  for (uint32_t base = 0; base < a.num_segments; base += kPrepThreads) {
+    const uint32_t s = base + tid;
+    uint32_t tiles = 0;
+    if (s < a.num_segments) {
+      const int64_t lo = a.offsets[s], hi = a.offsets[s + 1];
+      if (hi < lo || lo < 0) {
+        atomicOr(&bad, 1u);
+      } else {
+        const uint64_t n = uint64_t(hi - lo);
+        const uint32_t k = domain_bits_dev(n);
+        if (k > 32) atomicOr(&bad, 1u);
+        const uint64_t dom = uint64_t(1) << min(k, 40u);
+        tiles = (n == 0) ? 0u : uint32_t(min<uint64_t>((dom + a.tile - 1) / a.tile, 0xFFFFFFFFull));
+        a.segs[s].first = uint64_t(lo);
+        a.segs[s].n = n;
+        a.segs[s].k = k;
+        uint64_t st = a.seeds[s];
+        for (uint32_t r = 0; r < a.rounds; ++r) a.keys[uint64_t(s) * a.rounds + r] = uint32_t(splitmix64_next(st));
+      }
+    }
+    // block exclusive scan of `tiles`
+    uint32_t v = tiles;
+    const uint32_t lane = tid & 63u, warp = tid >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(v, off, 64);
+      if (lane >= uint32_t(off)) v += t;
+    }
+    if (lane == 63) warp_sums[warp] = v;
+    __syncthreads();
+    uint32_t warp_prefix = 0, block_total = 0;
+    for (uint32_t w = 0; w < kPrepThreads / 64; ++w) {
+      const uint32_t c = warp_sums[w];
+      warp_prefix += (w < warp) ? c : 0u;
+      block_total += c;
+    }
+    const uint64_t first = uint64_t(carry) + warp_prefix + v - tiles;
+    if (s < a.num_segments) {
+      a.segs[s].first_tile = uint32_t(min<uint64_t>(first, 0xFFFFFFFFull));
+      if (first + tiles > a.capacity) atomicOr(&bad, 1u);
+    }
+    __syncthreads();
+    if (tid == 0) carry = uint32_t(min<uint64_t>(uint64_t(carry) + block_total, 0xFFFFFFFFull));
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const uint32_t total = bad ? 0u : carry;
+    if (bad) atomicOr(&a.hdr->error, kErrBadBatch);
+    __hip_atomic_store(&a.hdr->batch_tiles, total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Marks which segment owns every tile: one wavefront per segment.
+__global__ __launch_bounds__(256) void batch_fill_kernel(const BatchArgs a) {
+  const uint32_t waves_total = gridDim.x * (blockDim.x / 64);
+  const uint32_t wave_global = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t total = __hip_atomic_load(&a.hdr->batch_tiles, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  if (total == 0) return;
+  for (uint32_t s = wave_global; s < a.num_segments; s += waves_total) {
+    const SegmentInfo si = a.segs[s];
+    if (si.n == 0) continue;
+    const uint64_t dom = uint64_t(1) << si.k;
+    const uint32_t tiles = uint32_t((dom + a.tile - 1) / a.tile);
+    for (uint32_t t = lane; t < tiles; t += 64) a.tile_segment[si.first_tile + t] = s;
+  }
+}
+
+// Zero-fills a workspace and records its status-word capacity in the header.
+__global__ void zero_fill_kernel(uint32_t* p, uint64_t words, uint32_t capacity_words) {
+  constexpr uint64_t kCapacityWord = offsetof(WorkspaceHeader, capacity) / sizeof(uint32_t);
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += uint64_t(gridDim.x) * blockDim.x)
+    p[i] = (i == kCapacityWord) ? capacity_words : 0u;
+}
+
+bool config_supported(const LaunchConfig& c) {
+#define BSD_MATCH(W, I, D) \
+  if (c.waves == W && c.items == I && c.depth == D) return true;
+  BSD_FOR_EACH_SHAPE(BSD_MATCH)
+#undef BSD_MATCH
+  return false;
+}
+
+// Workgroups to launch: one per tile (kGridOnePerTile), grid_mult per CU, or
+// (grid_mult == 0) as many as the device keeps resident at once, so the grid
+// is persistent and every workgroup loops over tickets.
+static uint32_t resident_groups(const void* fn, uint32_t threads, uint32_t num_cus) {
+  static std::map<std::pair<const void*, uint32_t>, uint32_t> cache;
+  auto key = std::make_pair(fn, threads);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(threads), 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const uint32_t g = uint32_t(per_cu) * num_cus;
+  cache[key] = g;
+  return g;
+}
+
+static uint32_t grid_for(uint64_t tiles, const LaunchConfig& cfg, uint32_t num_cus, const void* fn) {
+  uint64_t g = tiles;
+  if (cfg.grid_mult != kGridOnePerTile) {
+    const uint64_t persistent =
+        cfg.grid_mult == 0 ? resident_groups(fn, cfg.waves * 64, num_cus) : uint64_t(cfg.grid_mult) * num_cus;
+    if (persistent < g) g = persistent;
+  }
+  if (g == 0) g = 1;
+  return uint32_t(g);
+}
+
+hipError_t launch_single(const SingleArgs& a0, uint32_t eb, bool nt, const LaunchConfig& cfg0, uint32_t num_cus,
+                         hipStream_t stream) {
+  const bool wide = a0.domain > (uint64_t(1) << 32);
+  LaunchConfig cfg = cfg0;
+  if (wide) cfg.waves = kWideWaves, cfg.items = kWideItems, cfg.depth = 1;
+  SingleArgs a = a0;
+  a.nontemporal = nt ? 1u : 0u;
+  const bool odd = ((a.cs.w + a.cs.r) & 1u) != 0;
+  SingleFn fn = nullptr;
+  switch (eb) {
+    case 0: fn = pick_single_0(odd, wide, cfg); break;
+    case 1: fn = pick_single_1(odd, wide, cfg); break;
+    case 2: fn = pick_single_2(odd, wide, cfg); break;
+    case 4: fn = pick_single_4(odd, wide, cfg); break;
+    case 8: fn = pick_single_8(odd, wide, cfg); break;
+    case 16: fn = pick_single_16(odd, wide, cfg); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (!fn) return hipErrorInvalidValue;
+  const uint32_t grid = grid_for(a.num_tiles, cfg, num_cus, reinterpret_cast<const void*>(fn));
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * 64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& cfg, uint32_t num_cus,
+                          hipStream_t stream) {
+  BatchFn fn = nullptr;
+  switch (eb) {
+    case 1: fn = pick_batch_1(cfg); break;
+    case 2: fn = pick_batch_2(cfg); break;
+    case 4: fn = pick_batch_4(cfg); break;
+    case 8: fn = pick_batch_8(cfg); break;
+    case 16: fn = pick_batch_16(cfg); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (!fn) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_prepare_kernel, dim3(1), dim3(kPrepThreads), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t fill_blocks = std::max(1u, std::min(1024u, (a.num_segments + 3u) / 4u));
+  hipLaunchKernelGGL(batch_fill_kernel, dim3(fill_blocks), dim3(256), 0, stream, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // The grid never exceeds the workspace's tile capacity; surplus workgroups
+  // exit at their first ticket.
+  const uint32_t grid = grid_for(a.capacity, cfg, num_cus, reinterpret_cast<const void*>(fn));
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * 64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_workspace_init(void* ws, size_t bytes, hipStream_t stream) {
+  const uint64_t words = bytes / 4;
+  const uint64_t cap = bytes > sizeof(WorkspaceHeader) ? (bytes - sizeof(WorkspaceHeader)) / 8 : 0;
+  const uint32_t blocks = uint32_t(std::min<uint64_t>(1024, (words + 255) / 256 + 1));
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(ws), words,
+                     uint32_t(std::min<uint64_t>(cap, 0xFFFFFFFFull)));
+  return hipGetLastError();
+}
+
+}  // namespace bsd

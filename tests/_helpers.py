@@ -1,0 +1,32 @@
+"""Shared test helpers: oracle slices of large shuffles, computed in parallel
+threads (the oracle itself stays sequential; ctypes releases the GIL)."""
+from __future__ import annotations
+
+import concurrent.futures
+import os
+
+import numpy as np
+
+import oracle
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def kept_before(n: int, seed: int, rounds: int, i: int) -> int:
+    """Number of kept padded indices below i (the rank of the first output
+    produced at or after i), split across threads."""
+    if i == 0:
+        return 0
+    chunks = max(1, min(THREADS * 4, i // 65536))
+    bounds = np.linspace(0, i, chunks + 1, dtype=np.int64)
+    with concurrent.futures.ThreadPoolExecutor(THREADS) as ex:
+        parts = ex.map(lambda ab: oracle.count_kept(n, seed, rounds, int(ab[0]), int(ab[1])),
+                       zip(bounds[:-1], bounds[1:]))
+        return int(sum(parts))
+
+
+def oracle_window(x: np.ndarray, seed: int, rounds: int, i_begin: int, i_end: int) -> tuple[int, np.ndarray]:
+    """(first output position, oracle outputs) for padded indices [i_begin, i_end)."""
+    n = x.shape[0]
+    rank = kept_before(n, seed, rounds, i_begin)
+    return rank, oracle.shuffle_window(x, seed, rounds, i_begin, i_end)

@@ -1,0 +1,107 @@
+"""The C ABI on the host: the library loads, exports every declared symbol,
+and rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_06161_amd import binding as B
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = B.declared_functions()
+    assert "bs_shuffle" in names and "bs_shuffle_batched" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(9):
+        assert B.status_string(code).startswith("BS_")
+    assert "unknown" in B.status_string(99)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 16, 17, 100_000, (1 << 27) + 1, 10**9, (1 << 38) - 1])
+def test_domain_bits_matches_oracle(n):
+    assert B.bs_domain_bits(n) == oracle.domain_bits(n)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 42, 2**64 - 1])
+def test_round_keys_match_oracle(seed):
+    assert B.bs_round_keys(seed, 64) == list(oracle.round_keys(seed, 64))
+
+
+def test_workspace_bytes(lib):
+    w1 = B.bs_workspace_bytes(100_000)
+    assert w1 >= 256 + 8 * ((1 << 17) // 2048)
+    w2 = B.bs_workspace_bytes((1 << 27) + 1)
+    assert w2 >= 256 + 8 * ((1 << 28) // 2048)
+    wb = B.bs_workspace_bytes(445_000_000, 4096)
+    assert wb > w2
+
+
+FAKE_IN, FAKE_OUT = 1 << 40, 1 << 41  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("eb", [0, 3, 5, 12, 32])
+def test_rejects_bad_elem_bytes(eb):
+    assert B.bs_shuffle(FAKE_IN, FAKE_OUT, 10, eb, 1, 24, None, 0, None) == B.BS_EELEM
+
+
+def test_rejects_misaligned():
+    assert B.bs_shuffle(FAKE_IN + 2, FAKE_OUT, 10, 4, 1, 24, None, 0, None) == B.BS_EELEM
+    assert B.bs_shuffle(FAKE_IN, FAKE_OUT + 8, 10, 16, 1, 24, None, 0, None) == B.BS_EELEM
+
+
+def test_rejects_bad_rounds_and_sizes():
+    assert B.bs_shuffle(FAKE_IN, FAKE_OUT, 10, 4, 1, 65, None, 0, None) == B.BS_EINVAL
+    assert B.bs_shuffle(FAKE_IN, FAKE_OUT, 1 << 38, 4, 1, 24, None, 0, None) == B.BS_EINVAL
+
+
+def test_rejects_null_and_alias():
+    assert B.bs_shuffle(None, FAKE_OUT, 10, 4, 1, 24, None, 0, None) == B.BS_EINVAL
+    assert B.bs_shuffle(FAKE_IN, None, 10, 4, 1, 24, None, 0, None) == B.BS_EINVAL
+    assert B.bs_shuffle(FAKE_IN, FAKE_IN, 10, 4, 1, 24, None, 0, None) == B.BS_EALIAS
+    assert B.bs_shuffle(FAKE_IN, FAKE_IN + 36, 10, 4, 1, 24, None, 0, None) == B.BS_EALIAS
+    assert B.bs_shuffle(FAKE_IN + 36, FAKE_IN, 10, 4, 1, 24, None, 0, None) == B.BS_EALIAS
+
+
+def test_zero_items_is_a_noop():
+    assert B.bs_shuffle(None, None, 0, 4, 1, 24, None, 0, None) == B.BS_OK
+    assert B.bs_shuffle_batched(None, None, None, None, 0, 0, 4, 24, None, 0, None) == B.BS_OK
+
+
+def test_batched_rejects_bad_arguments():
+    assert B.bs_shuffle_batched(FAKE_IN, FAKE_OUT, None, 1, 3, 10, 4, 24, None, 0, None) == B.BS_EINVAL
+    assert B.bs_shuffle_batched(FAKE_IN, FAKE_OUT, 1, 1, 3, 10, 3, 24, None, 0, None) == B.BS_EELEM
+    assert B.bs_shuffle_batched(FAKE_IN, FAKE_IN, 8, 8, 3, 10, 4, 24, None, 0, None) == B.BS_EALIAS
+    assert B.bs_shuffle_batched(FAKE_IN, FAKE_OUT, 8, 8, 3, 10, 4, 99, None, 0, None) == B.BS_EINVAL
+
+
+def test_user_workspace_too_small_is_rejected():
+    assert B.bs_shuffle(FAKE_IN, FAKE_OUT, 100_000, 4, 1, 24, 1 << 42, 64, None) == B.BS_ENOMEM
+
+
+def test_config_round_trip():
+    before = B.bs_get_config()
+    assert B.bs_set_config(8, 8, 2, 2) == B.BS_OK
+    assert B.bs_get_config() == (8, 8, 2, 2)
+    assert B.bs_set_config(3, 8, 1, 0) == B.BS_EINVAL
+    assert B.bs_set_config(8, 8, 1, 0) == B.BS_EINVAL
+    assert B.bs_set_config(8, 16, 1, 65) == B.BS_EINVAL
+    assert B.bs_set_config(8, 16, 1, B.GRID_ONE_PER_TILE) == B.BS_OK
+    assert B.bs_set_config(0, 0, 0, 0) == B.BS_OK
+    assert B.bs_get_config() == before
+
+
+def test_probe_argument_checks():
+    assert B.bs_probe_copy(FAKE_IN + 4, FAKE_OUT, 64, None) == B.BS_EELEM
+    assert B.bs_probe_copy(FAKE_IN, FAKE_IN + 16, 64, None) == B.BS_EALIAS
+    assert B.bs_probe_gather(FAKE_IN, 10, FAKE_OUT, None, 10, 4, None) == B.BS_EINVAL
+    assert B.bs_probe_cipher_scan(10, 1, 99, None, 0, None) == B.BS_EINVAL
