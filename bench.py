@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the bijective shuffle on one MI355X.
+
+One step = one bs_shuffle of the headline workload: n = 2^27 + 1 uint32 values
+drawn uniform from [0, 2^32) with PCG64(7), seed 7, 24 rounds (the paper's
+setting), padded domain 2^28.  That single fused kernel covers every step of
+the method: parameters and round keys, the cipher, keep flags and scan with
+decoupled look-back, the random gather and the output stores.
+
+Prints ONE JSON line:
+  value        Gelem/s over the K timed steps (inputs resident in HBM)
+  roofline     the fused kernel against the HBM peak: algorithmic bytes
+               (one read + one write of every record, 8 B per uint32 item)
+               per launch over the kernel's average duration (HIP events on
+               the launch stream), plus the HBM traffic measured by rocprofv3
+               when a summary for the current kernel sources is committed
+  cpu_baseline the sequential CPU oracle on a bounded sample (one thread)
+  ceilings     measured device copy and random-gather rates, the cipher+scan
+               kernel alone, the 4-round and power-of-two variants
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+N_HEADLINE = (1 << 27) + 1
+SEED = 7
+ROUNDS = 24
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_shuffle_u32_n2p27p1.txt")
+KERNEL_SOURCES = [
+    "paper_2106_06161_amd/csrc/shuffle_impl.h",
+    "paper_2106_06161_amd/csrc/tile_scan.h",
+    "paper_2106_06161_amd/csrc/vphilox_round.h",
+    "paper_2106_06161_amd/csrc/kernels.h",
+    "paper_2106_06161_amd/csrc/api.hip",
+]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse_args():
+    p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--rounds", type=int, default=ROUNDS)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-ceilings", action="store_true")
+    p.add_argument("--profile", action="store_true",
+                   help="profiler run: one copy of known size, then the steps; no extras")
+    return p.parse_args()
+
+
+class Timer:
+    """HIP events on one stream (torch's current stream, where the library launches)."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, fn, iters: int, warm: int = 2) -> float:
+        torch = self.torch
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(iters)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(iters)]
+        for i in range(iters):
+            starts[i].record(self.stream)
+            fn()
+            ends[i].record(self.stream)
+        torch.cuda.synchronize()
+        return sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / iters * 1e-3
+
+
+def committed_traffic(digest: str):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.loads(fh.read())
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_digest") != digest:
+        return None
+    return rec
+
+
+def cpu_baseline() -> dict:
+    """The oracle, single thread, on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2106_06161_amd import workloads as W
+
+    n = (1 << 25) + 1  # same padding ratio as the headline (domain 2^26)
+    x = W.uniform_u32(n, seed=SEED)
+    t0 = time.perf_counter()
+    out = oracle.shuffle(x, SEED, ROUNDS)
+    dt = time.perf_counter() - t0
+    assert out.shape == x.shape and np.uint64(out.sum(dtype=np.uint64)) == np.uint64(x.sum(dtype=np.uint64))
+    return {
+        "value": n / dt / 1e9,
+        "unit": "Gelem/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"n=2^25+1 uint32 uniform (PCG64 seed 7), seed 7, {ROUNDS} rounds, domain 2^26, one run "
+                  f"({dt:.1f} s) on {platform.processor() or platform.machine()}",
+    }
+
+
+def main() -> int:
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the shuffle is single-device; see the sharding notes in DESIGN.md)", flush=True)
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_2106_06161_amd as bs
+    from paper_2106_06161_amd import binding as B
+    from paper_2106_06161_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+    timer = Timer(torch, stream)
+    rounds = args.rounds
+
+    log("bench: generating the headline input (n=2^27+1 uint32, PCG64 seed 7)")
+    x_np = W.uniform_u32(N_HEADLINE, seed=SEED)
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.empty_like(x)
+    del x_np
+    ws = bs.make_workspace(bs.workspace_bytes(N_HEADLINE), device=dev)
+
+    if args.profile:
+        nb = (N_HEADLINE * 4) // 16 * 16
+        B._check(B.bs_probe_copy(x.data_ptr(), y.data_ptr(), nb, sp), "bs_probe_copy")
+        torch.cuda.synchronize()
+        log(f"bench: copy probe of {nb} bytes done")
+
+    def step():
+        bs.shuffle(x, SEED, rounds, out=y, workspace=ws)
+
+    log(f"bench: {args.warmup} warmup steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, synchronized on both sides
+    log(f"bench: timing {args.steps} steps")
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev0[i].record(stream)
+        step()
+        ev1[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_s = sum(a.elapsed_time(b) for a, b in zip(ev0, ev1)) / args.steps * 1e-3
+    err = bs.workspace_error(ws)
+    if err != 0:
+        log(f"bench: device-side error {B.status_string(err)}")
+        return 1
+    log(f"bench: {wall / args.steps * 1e3:.3f} ms/step wall, {kernel_s * 1e3:.3f} ms kernel")
+
+    alg_bytes = 2 * 4 * N_HEADLINE
+    achieved = alg_bytes / kernel_s / 1e9
+    digest = kernel_source_digest()
+    traffic = committed_traffic(digest)
+    result = {
+        "metric": "Gelem/s + % HBM peak at n=2^27+1 u32; batched vs per-call; p99 latency",
+        "value": N_HEADLINE * args.steps / wall / 1e9,
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "single bijective shuffle, n=2^27+1 uint32 uniform (PCG64 seed 7), seed 7, "
+                        f"{rounds} rounds, domain 2^28",
+            "n": N_HEADLINE, "elem_bytes": 4, "rounds": rounds, "seed": SEED,
+            "launch": dict(zip(("waves", "items", "depth", "grid_mult"), B.bs_get_config())),
+        },
+        "pct_hbm_peak": 100.0 * (alg_bytes * args.steps / wall / 1e9) / HBM_PEAK_GBPS,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
+            "kernel": "bsd::shuffle_single_kernel<4, even k, 16 waves, 16 items, depth 1>",
+            "kernel_ms": kernel_s * 1e3,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "kernel_source_digest": digest,
+        },
+    }
+    if args.profile:
+        print(json.dumps(result), flush=True)
+        return 0
+
+    if not args.no_ceilings:
+        log("bench: ceilings (copy, random gather, cipher+scan alone, variants)")
+        ceil = {}
+        nb = (N_HEADLINE * 4) // 16 * 16
+        t = timer.run(lambda: B.bs_probe_copy(x.data_ptr(), y.data_ptr(), nb, sp), 10)
+        ceil["copy_GBps"] = 2 * nb / t / 1e9
+        perm = torch.randperm(N_HEADLINE, device=dev, dtype=torch.int64).to(torch.int32)
+        t = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), N_HEADLINE, y.data_ptr(), perm.data_ptr(),
+                                                N_HEADLINE, 4, sp), 10)
+        del perm
+        ceil["gather_index_array_ms"] = t * 1e3
+        ceil["gather_index_array_Gelem_s"] = N_HEADLINE / t / 1e9
+        t = timer.run(lambda: B.bs_probe_cipher_scan(N_HEADLINE, SEED, rounds, ws.data_ptr(), ws.numel(), sp), 10)
+        ceil["cipher_scan_only_ms"] = t * 1e3
+        t4 = timer.run(lambda: bs.shuffle(x, SEED, 4, out=y, workspace=ws), 10)
+        ceil["shuffle_4_rounds_ms"] = t4 * 1e3
+        ceil["shuffle_4_rounds_Gelem_s"] = N_HEADLINE / t4 / 1e9
+        xp, yp = x[: 1 << 27], y[: 1 << 27]
+        tp = timer.run(lambda: bs.shuffle(xp, SEED, rounds, out=yp, workspace=ws), 10)
+        ceil["shuffle_pow2_n2p27_ms"] = tp * 1e3
+        ceil["shuffle_pow2_n2p27_Gelem_s"] = (1 << 27) / tp / 1e9
+        ceil["shuffle_pct_of_copy"] = 100.0 * achieved / ceil["copy_GBps"]
+        ceil["shuffle_pct_of_gather"] = 100.0 * ceil["gather_index_array_ms"] / (kernel_s * 1e3)
+        result["ceilings"] = ceil
+        if bs.workspace_error(ws) != 0:
+            log("bench: device-side error in ceilings")
+            return 1
+
+    if not args.no_cpu_baseline:
+        log("bench: CPU baseline (oracle, one thread, bounded sample)")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -78,7 +78,7 @@ BatchLayout batch_layout(uint64_t items, uint32_t segments) {
   l.status = kHeaderBytes;
   l.segs = align256(l.status + l.capacity * 8);
   l.keys = align256(l.segs + size_t(segments) * sizeof(bsd::SegmentInfo));
-  l.tile_segment = align256(l.keys + size_t(segments) * BS_MAX_ROUNDS * 4);
+  l.tile_segment = align256(l.keys + size_t(segments) * (BS_MAX_ROUNDS + 1) * 4);
   l.total = align256(l.tile_segment + l.capacity * 4);
   return l;
 }
@@ -264,6 +264,8 @@ bs_status bs_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes,
   a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
   a.rounds = rounds;
   bs_round_keys(seed, rounds, a.key);
+  for (uint32_t r = 0; r < rounds; ++r) a.key[r] &= a.cs.wmask;  // only the half width reaches the state
+  a.key[rounds] = 0;
 
   std::lock_guard<std::mutex> lock(g_mu);
   const bsd::LaunchConfig cfg = g_cfg;
@@ -357,6 +359,8 @@ extern "C" bs_status bs_probe_cipher_scan(uint64_t n, uint64_t seed, uint32_t ro
   a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
   a.rounds = rounds;
   bs_round_keys(seed, rounds, a.key);
+  for (uint32_t r = 0; r < rounds; ++r) a.key[r] &= a.cs.wmask;
+  a.key[rounds] = 0;
   std::lock_guard<std::mutex> lock(g_mu);
   const bsd::LaunchConfig cfg = g_cfg;
   const uint64_t tile = k > 32 ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;

@@ -24,7 +24,7 @@ struct SingleArgs {
   uint32_t nontemporal;  // 1: output stores bypass cache retention
   WorkspaceHeader* hdr;
   uint64_t* status;
-  uint32_t key[kMaxRounds];
+  uint32_t key[kMaxRounds + 1];  // round keys masked to the half width, then 0
 };
 
 // Per-segment record written by the batch preparation kernel.
@@ -48,7 +48,7 @@ struct BatchArgs {
   WorkspaceHeader* hdr;
   uint64_t* status;
   SegmentInfo* segs;        // num_segments records
-  uint32_t* keys;           // num_segments * rounds round keys
+  uint32_t* keys;           // num_segments * (rounds + 1): masked keys, then 0
   uint32_t* tile_segment;   // capacity entries: segment owning each tile
 };
 
@@ -74,7 +74,8 @@ using BatchFn = void (*)(BatchArgs);
 
 // Per-element-size kernel selection (one translation unit each).
 // Tile shapes that are compiled: (waves per workgroup, indices per lane, depth).
-#define BSD_FOR_EACH_SHAPE(X) X(4, 16, 2) X(8, 16, 2) X(8, 16, 1) X(16, 16, 1) X(16, 8, 1) X(8, 8, 2) X(4, 16, 1)
+#define BSD_FOR_EACH_SHAPE(X) \
+  X(4, 16, 2) X(8, 16, 2) X(8, 16, 1) X(16, 16, 1) X(16, 8, 1) X(8, 8, 2) X(4, 16, 1) X(16, 16, 2) X(16, 8, 2)
 // Shape used when the index space needs 64 bits (k > 32).
 constexpr uint32_t kWideWaves = 8, kWideItems = 16;
 

@@ -128,9 +128,10 @@ constexpr uint32_t kDropped = 0xFFFFFFFFu;
 template <int EB, int ITEMS>
 struct PendingTile {
   typename Payload<EB>::T val[ITEMS];  // gathered records (loads may be in flight)
-  uint32_t rank[ITEMS];                // wave-local output rank, kDropped if not kept
+  uint32_t keep_bits;                  // bit j: this lane keeps its index of item j
   uint32_t wave_count;                 // kept indices of this wave (uniform)
 };
+static_assert(kDropped != 0, "");
 
 template <int EB, bool ODD, int WAVES, int ITEMS, bool WIDE>
 __device__ __forceinline__ void tile_gather(PendingTile<EB, ITEMS>& t, const uint8_t* __restrict__ in, uint64_t n,
@@ -139,35 +140,49 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, ITEMS>& t, const uin
   using Idx = std::conditional_t<WIDE, uint64_t, uint32_t>;
   constexpr uint32_t kTile = 64u * WAVES * ITEMS;
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = threadIdx.x >> 6;
-  const Idx base = Idx(tile_in_segment) * Idx(kTile) + Idx(wave * (64u * ITEMS) + lane);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Idx tile_base = Idx(tile_in_segment) * Idx(kTile);
+  const Idx base = tile_base + Idx(wave * (64u * ITEMS) + lane);
+  // Tiles wholly inside the padded domain (every tile once 2^k >= tile size)
+  // skip the per-index domain test.
+  const bool whole_tile = uint64_t(tile_base) + kTile <= domain;
 
-  uint32_t L[ITEMS], R[ITEMS];
+  // The cipher runs in sub-rounds of kSub items: the loads issued for one
+  // sub-round are in flight while the next sub-round computes, and only kSub
+  // cipher states are live at a time (register pressure sets occupancy).
+  constexpr int kSub = ITEMS >= 16 ? 8 : ITEMS;
   const uint32_t wmask24 = cs.wmask & 0xFFFFFFu;
+  const Idx x_last = Idx(domain - 1);
+  const Idx y_last = Idx(n - 1);
+  uint32_t wave_count = 0, keep_bits = 0;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const Idx x = base + Idx(j * 64);
-    L[j] = uint32_t(x >> cs.r) & wmask24;
-    R[j] = uint32_t(x);
-  }
-  vp_encrypt<ODD, ITEMS>(L, R, cs, rounds, keys);
-
-  uint32_t wave_count = 0;
+  for (int s0 = 0; s0 < ITEMS; s0 += kSub) {
+    uint32_t L[kSub], R[kSub];
+    uint32_t in_domain = whole_tile ? ~0u : 0u;  // bit j: index of item s0+j is < 2^k
+    Idx x = base + Idx(s0 * 64);
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const Idx x = base + Idx(j * 64);
-    const Idx y = (Idx(L[j]) << cs.r) | Idx(R[j] & cs.rmask);
-    const bool keep = (uint64_t(x) < domain) && (uint64_t(y) < n);
-    const uint64_t m = __ballot(keep);
-    const uint32_t below =
-        __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-    t.rank[j] = keep ? wave_count + below : kDropped;
-    if constexpr (EB > 0) {
-      if (keep) t.val[j] = load_record<EB>(in, uint64_t(y));
+    for (int j = 0; j < kSub; ++j, x += 64) {
+      L[j] = uint32_t(x >> cs.r) & wmask24;
+      R[j] = uint32_t(x);
+      if (!whole_tile) in_domain |= (x <= x_last) ? (1u << j) : 0u;
     }
-    wave_count += uint32_t(__builtin_popcountll(m));
+    vp_encrypt<ODD, kSub>(L, R, cs, rounds, keys);
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) {
+      const Idx y = (Idx(L[j]) << cs.r) | Idx(R[j] & cs.rmask);
+      // keep: the padded index is inside the domain and its image is < n
+      // (as "<= last" so the narrow path compares in 32 bits: n, 2^k <= 2^32)
+      const bool keep = ((in_domain >> j) & 1u) && (y <= y_last);
+      const uint64_t m = __ballot(keep);
+      keep_bits |= keep ? (1u << (s0 + j)) : 0u;
+      if constexpr (EB > 0) {
+        if (keep) t.val[s0 + j] = load_record<EB>(in, uint64_t(y));
+      }
+      wave_count += uint32_t(__builtin_popcountll(m));
+    }
   }
   t.wave_count = wave_count;
+  t.keep_bits = keep_bits;
 }
 
 // Returns this wave's output base: kept indices before the tile (look-back)
@@ -177,7 +192,7 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
                                               uint32_t status_idx, uint32_t tag, WorkspaceHeader* hdr,
                                               TileLds<WAVES>& lds) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (lane == 0) lds.wave_count[wave] = wave_count;
   __syncthreads();
   uint32_t wave_exclusive = 0, tile_total = 0;
@@ -198,24 +213,30 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
   return lds.tile_exclusive + wave_exclusive;
 }
 
-// Positions are < n by construction; the bound check only keeps a timed-out
-// look-back from writing outside the buffer.
+// Writes the kept records: item j's kept lanes go to consecutive positions
+// prefix + (kept before item j in this wave) + (kept lanes below this lane),
+// the ballot and rank being recomputed here from the keep bits.  Positions
+// are < n by construction; the bound check only keeps a timed-out look-back
+// from writing outside the buffer.
 template <int EB, int ITEMS>
 __device__ __forceinline__ void tile_store(const PendingTile<EB, ITEMS>& t, uint8_t* __restrict__ out, uint64_t n,
                                            uint64_t prefix, bool nontemporal) {
   if constexpr (EB > 0) {
-    if (nontemporal) {
+    uint64_t base = prefix;
 #pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t pos = prefix + t.rank[j];
-        if (t.rank[j] != kDropped && pos < n) store_record<EB, true>(out, pos, t.val[j]);
+    for (int j = 0; j < ITEMS; ++j) {
+      const bool keep = (t.keep_bits >> j) & 1u;
+      const uint64_t m = __ballot(keep);
+      const uint32_t below =
+          __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+      const uint64_t pos = base + below;
+      if (keep && pos < n) {
+        if (nontemporal)
+          store_record<EB, true>(out, pos, t.val[j]);
+        else
+          store_record<EB, false>(out, pos, t.val[j]);
       }
-    } else {
-#pragma unroll
-      for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t pos = prefix + t.rank[j];
-        if (t.rank[j] != kDropped && pos < n) store_record<EB, false>(out, pos, t.val[j]);
-      }
+      base += uint64_t(__builtin_popcountll(m));
     }
   }
 }
@@ -225,8 +246,15 @@ __device__ __forceinline__ void tile_store(const PendingTile<EB, ITEMS>& t, uint
 // gather phase of the next tile (cipher + loads issued) runs while the loads
 // of the current tile are outstanding, then the current tile is stored.
 // DEPTH 1 finishes each tile before starting the next (fewer registers).
+// Minimum waves per SIMD the register budget is sized for (HIP's second
+// launch-bounds argument).  Two 16-wave groups per CU (8 waves per SIMD, at
+// most 64 VGPRs) keep one group's gathers in flight while the other computes.
+template <int WAVES, int DEPTH>
+constexpr int kMinWavesPerSimd = 1;
+
 template <int EB, bool ODD, int WAVES, int ITEMS, int DEPTH, bool WIDE>
-__global__ __launch_bounds__(WAVES * 64) void shuffle_single_kernel(const SingleArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void shuffle_single_kernel(
+    const SingleArgs a) {
   __shared__ TileLds<WAVES> lds;
   group_begin(a.hdr, lds);
   const uint32_t gen = lds.gen;
@@ -300,7 +328,7 @@ __device__ __forceinline__ BatchTile batch_tile(const BatchArgs& a, uint32_t til
   b.cs.r = k - b.cs.w;
   b.cs.wmask = (1u << b.cs.w) - 1u;
   b.cs.rmask = (1u << b.cs.r) - 1u;
-  b.keys = a.keys + uint64_t(s) * a.rounds;
+  b.keys = a.keys + uint64_t(s) * (a.rounds + 1);
   b.in = a.in + si.first * uint64_t(EB);
   b.out = a.out + si.first * uint64_t(EB);
   b.n = si.n;
@@ -320,7 +348,8 @@ __device__ __forceinline__ void batch_gather(PendingTile<EB, ITEMS>& t, const Ba
 }
 
 template <int EB, int WAVES, int ITEMS, int DEPTH>
-__global__ __launch_bounds__(WAVES * 64) void shuffle_batched_kernel(const BatchArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void shuffle_batched_kernel(
+    const BatchArgs a) {
   __shared__ TileLds<WAVES> lds;
   group_begin(a.hdr, lds);
   const uint32_t gen = lds.gen;

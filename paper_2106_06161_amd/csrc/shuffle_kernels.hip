@@ -39,8 +39,12 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(const Batch
         a.segs[s].first = uint64_t(lo);
         a.segs[s].n = n;
         a.segs[s].k = k;
+        // round keys masked to the half width, then a 0 (see vp_encrypt)
+        const uint32_t wmask = (1u << (k >> 1)) - 1u;
+        uint32_t* keys = a.keys + uint64_t(s) * (a.rounds + 1);
         uint64_t st = a.seeds[s];
-        for (uint32_t r = 0; r < a.rounds; ++r) a.keys[uint64_t(s) * a.rounds + r] = uint32_t(splitmix64_next(st));
+        for (uint32_t r = 0; r < a.rounds; ++r) keys[r] = uint32_t(splitmix64_next(st)) & wmask;
+        keys[a.rounds] = 0;
       }
     }
     // block exclusive scan of `tiles`

@@ -40,36 +40,50 @@ struct CipherShape {
   uint32_t rmask;  // 2^r - 1
 };
 
-// L < 2^24 is required; callers pass wmask & 0xFFFFFF so the compiler can see
-// it and select the 24-bit multiply.
+// One round.  R arrives with this round's key already xored into it
+// (Rk = R ^ key_r) and leaves with the next round's key xored in, so the key
+// never costs an instruction on the L path and R' is a fresh register (the
+// 64-bit product's halves are not carried across rounds).  Keys must be
+// masked to the half width, so bit w of Rk is still the extra bit b; the key
+// after the last round is 0, which leaves the plain R.  L < 2^24 is required;
+// callers pass wmask & 0xFFFFFF so the compiler can see it.
 template <bool ODD>
-__device__ __forceinline__ void vp_round(uint32_t& L, uint32_t& R, uint32_t key, uint32_t w, uint32_t wmask24) {
-  const uint64_t p = uint64_t(kM0Lo) * uint64_t(L);
+__device__ __forceinline__ void vp_round(uint32_t& L, uint32_t& Rk, uint32_t key_next, uint32_t w,
+                                         uint32_t wmask24) {
+  const uint64_t p = uint64_t(kM0Lo) * uint64_t(L);  // v_mad_u64_u32
   const uint32_t lo = uint32_t(p);
-  const uint32_t hi = uint32_t(p >> 32) + kM0Hi24 * L;
-  const uint32_t Ln = (hi ^ key ^ R) & wmask24;
+  // hi = (M0hi mod 2^24) * L + high word of M0lo * L.  Written as one
+  // v_mad_u32_u24: left to itself the compiler widens this into a second
+  // 64-bit multiply-add plus register-pair copies.
+  uint32_t hi;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(hi) : "s"(kM0Hi24), "v"(L), "v"(uint32_t(p >> 32)));
+  const uint32_t Ln = (hi ^ Rk) & wmask24;  // F(L) xor R (key already in Rk)
   uint32_t Rn;
   if constexpr (ODD) {
-    Rn = (lo << 1) | __builtin_amdgcn_ubfe(R, w, 1u);
+    Rn = ((lo << 1) | __builtin_amdgcn_ubfe(Rk, w, 1u)) ^ key_next;
   } else {
-    Rn = lo;
+    Rn = lo ^ key_next;
   }
   L = Ln;
-  R = Rn;
+  Rk = Rn;
 }
 
 // Encrypts ITEMS independent blocks, interleaved round by round so that the
-// ITEMS dependency chains fill the VALU pipeline.  Round keys are read one
-// per round from uniform memory (scalar loads), which keeps them out of the
+// ITEMS dependency chains fill the VALU pipeline.  keys[0..rounds] are the
+// round keys masked to the half width followed by a 0; they are read one per
+// round from uniform memory (scalar loads), which keeps them out of the
 // scalar register file.
 template <bool ODD, int ITEMS>
 __device__ __forceinline__ void vp_encrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[ITEMS], const CipherShape& cs,
                                            uint32_t rounds, const uint32_t* __restrict__ keys) {
   const uint32_t wmask24 = cs.wmask & 0xFFFFFFu;
-  for (uint32_t rr = 0; rr < rounds; ++rr) {
-    const uint32_t key = keys[rr];
+  const uint32_t key0 = keys[0];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) vp_round<ODD>(L[j], R[j], key, cs.w, wmask24);
+  for (int j = 0; j < ITEMS; ++j) R[j] ^= key0;
+  for (uint32_t rr = 0; rr < rounds; ++rr) {
+    const uint32_t key_next = keys[rr + 1];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) vp_round<ODD>(L[j], R[j], key_next, cs.w, wmask24);
   }
 }
 
