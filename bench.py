@@ -17,6 +17,8 @@ Prints ONE JSON line:
   cpu_baseline the sequential CPU oracle on a bounded sample (one thread)
   ceilings     measured device copy and random-gather rates, the cipher+scan
                kernel alone, the 4-round and power-of-two variants
+  batched      4,096 independent shuffles in one launch vs 4,096 calls
+  serving      the continuous-batching server: capacity, p50 / p99 latency
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -67,6 +69,9 @@ def parse_args():
     p.add_argument("--rounds", type=int, default=ROUNDS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-ceilings", action="store_true")
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-serving", action="store_true")
+    p.add_argument("--serve-requests", type=int, default=2000)
     p.add_argument("--profile", action="store_true",
                    help="profiler run: one copy of known size, then the steps; no extras")
     return p.parse_args()
@@ -124,6 +129,93 @@ def cpu_baseline() -> dict:
         "kind": "oracle",
         "sample": f"n=2^25+1 uint32 uniform (PCG64 seed 7), seed 7, {ROUNDS} rounds, domain 2^26, one run "
                   f"({dt:.1f} s) on {platform.processor() or platform.machine()}",
+    }
+
+
+def bench_batched(torch, bs, W, np, dev, stream, timer, rounds) -> dict:
+    """4,096 independent shuffles: one batched launch (graph replay) against
+    4,096 bs_shuffle calls on one stream, eager and captured in one graph."""
+    b = W.batch(4096, 100, 1_000_000, seed=3)
+    total, S = b["total"], 4096
+    x = torch.arange(total, dtype=torch.int64, device=dev).to(torch.int32)
+    y = torch.empty_like(x)
+    off = torch.from_numpy(b["offsets"]).to(dev)
+    sd = torch.from_numpy(b["seeds"].view(np.int64)).to(dev)
+    ws_b = bs.make_workspace(bs.workspace_bytes(total, S), device=dev)
+    ws_s = bs.make_workspace(bs.workspace_bytes(int(b["sizes"].max())), device=dev)
+    offsets = [int(v) for v in b["offsets"]]
+    seeds = [int(v) for v in b["seeds"]]
+    views = [(x[offsets[s]:offsets[s + 1]], y[offsets[s]:offsets[s + 1]], seeds[s]) for s in range(S)
+             if offsets[s + 1] > offsets[s]]
+
+    def one_batched():
+        bs.shuffle_batched(x, off, sd, rounds, out=y, workspace=ws_b)
+
+    def per_call():
+        for xs, ys, sdv in views:
+            bs.shuffle(xs, sdv, rounds, out=ys, workspace=ws_s)
+
+    def graph_of(fn):
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            fn()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            fn()
+        torch.cuda.synchronize()
+        return g
+
+    t_batched_eager = timer.run(one_batched, 5)
+    g1 = graph_of(one_batched)
+    t_batched_graph = timer.run(g1.replay, 5)
+    t0 = time.perf_counter()
+    per_call()
+    torch.cuda.synchronize()
+    t_calls_eager = time.perf_counter() - t0
+    t_calls_eager = min(t_calls_eager, timer.run(per_call, 2, warm=0))
+    gN = graph_of(per_call)
+    t_calls_graph = timer.run(gN.replay, 3)
+    err = bs.workspace_error(ws_b) or bs.workspace_error(ws_s)
+    del g1, gN
+    return {
+        "workload": "4,096 shuffles, sizes floor(exp(U(ln 100, ln 1e6))) from PCG64(3), uint32 payload, "
+                    f"{rounds} rounds, per-segment 64-bit seeds",
+        "total_items": total,
+        "batched_graph_ms": t_batched_graph * 1e3,
+        "batched_eager_ms": t_batched_eager * 1e3,
+        "per_call_eager_ms": t_calls_eager * 1e3,
+        "per_call_graph_ms": t_calls_graph * 1e3,
+        "batched_Gelem_s": total / t_batched_graph / 1e9,
+        "per_call_Gelem_s": total / t_calls_eager / 1e9,
+        "speedup_vs_per_call_eager": t_calls_eager / t_batched_graph,
+        "speedup_vs_per_call_graph": t_calls_graph / t_batched_graph,
+        "device_error": int(err),
+    }
+
+
+def bench_serving(rounds: int, count: int) -> dict:
+    """The continuous-batching server: closed-loop capacity (every request
+    arrives at once), then Poisson arrivals at 0.8x that rate."""
+    from paper_2106_06161_amd.serve import HipExecutor, ShuffleServer, make_requests
+
+    ex = HipExecutor(streams=4, rounds=rounds, pool_items=1 << 27)
+    srv = ShuffleServer(ex, budget_bytes=32 << 30)
+    cap = srv.run(make_requests(count, 1000, 100_000_000, qps=1e12, seed=5)).summary()
+    qps = 0.8 * cap["requests_per_s"]
+    run = srv.run(make_requests(count, 1000, 100_000_000, qps=qps, seed=6)).summary()
+    return {
+        "workload": f"{count} requests per run, sizes floor(exp(U(ln 1e3, ln 1e8))), dtype uniform over "
+                    "uint32/int64/float32, 64-bit seeds (PCG64 5 and 6); payloads resident in HBM; "
+                    "HBM budget 32 GiB of outputs, 4 streams, requests <= 2^20 records coalesced",
+        "closed_loop": cap,
+        "open_loop_qps": qps,
+        "open_loop": run,
+        "p50_ms": run["latency_p50_ms"],
+        "p99_ms": run["latency_p99_ms"],
+        "device_error": int(ex.check_errors()),
     }
 
 
@@ -255,6 +347,15 @@ def main() -> int:
         if bs.workspace_error(ws) != 0:
             log("bench: device-side error in ceilings")
             return 1
+
+    if not args.no_batched:
+        log("bench: batched vs per-call (4,096 segments, log-uniform sizes in [100, 10^6], PCG64 seed 3)")
+        result["batched"] = bench_batched(torch, bs, W, np, dev, stream, timer, rounds)
+
+    if not args.no_serving:
+        log(f"bench: serving ({args.serve_requests} requests, sizes log-uniform in [10^3, 10^8], "
+            "dtype uniform over uint32/int64/float32)")
+        result["serving"] = bench_serving(rounds, args.serve_requests)
 
     if not args.no_cpu_baseline:
         log("bench: CPU baseline (oracle, one thread, bounded sample)")

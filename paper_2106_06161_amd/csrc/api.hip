@@ -315,6 +315,7 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
   a.out = static_cast<uint8_t*>(out);
   a.offsets = offsets;
   a.seeds = seeds;
+  a.total_items = total_items;
   a.num_segments = num_segments;
   a.rounds = rounds;
   a.capacity = uint32_t(lay.capacity);

@@ -40,6 +40,7 @@ struct BatchArgs {
   uint8_t* out;
   const int64_t* offsets;  // device, num_segments + 1
   const uint64_t* seeds;   // device, num_segments
+  uint64_t total_items;     // records in in/out; every offset must be <= this
   uint32_t num_segments;
   uint32_t rounds;
   uint32_t capacity;        // status words the workspace holds (= max tiles)

@@ -10,7 +10,8 @@ namespace bsd {
 
 // One workgroup of 1024 threads: per-segment sizes, domain bits, round keys,
 // and the exclusive scan of tile counts.  Rejects the whole batch (no tile is
-// run) if the offsets are malformed, a segment needs more than 32 index bits,
+// run) if the offsets are malformed (offsets[0] != 0, decreasing, or past
+// total_items), a segment needs more than 32 index bits,
 // or the tiles exceed the workspace.
 constexpr uint32_t kPrepThreads = 1024;
 __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(const BatchArgs a) {
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(const Batch
     uint32_t tiles = 0;
     if (s < a.num_segments) {
       const int64_t lo = a.offsets[s], hi = a.offsets[s + 1];
-      if (hi < lo || lo < 0) {
+      if (hi < lo || lo < 0 || uint64_t(hi) > a.total_items) {
         atomicOr(&bad, 1u);
       } else {
         const uint64_t n = uint64_t(hi - lo);

@@ -1,0 +1,376 @@
+"""Continuous-batching shuffle server (single GPU).
+
+Requests (size n, payload dtype, 64-bit seed, arrival time) are served in
+real time:
+
+  admission   a request is admitted once it has arrived and its output
+              bytes fit the HBM budget (FIFO: a request that does not fit
+              holds back the ones behind it);
+  coalescing  admitted requests of at most `small_items` records are grouped
+              by element size into one bs_shuffle_batched launch (their inputs
+              sit back to back in a device-resident pool); larger requests get
+              a bs_shuffle launch of their own;
+  overlap     launches go round-robin to several HIP streams, so requests that
+              arrive while others run are admitted as memory frees up and
+              their work overlaps on the device;
+  completion  an event per launch; a request's latency is the time from its
+              scheduled arrival to the moment its launch is seen complete.
+
+Every request's result depends only on its own input bytes, n, dtype size,
+seed and the round count: grouping, stream and timing never change a byte.
+
+The executor owns all device work (HipExecutor); the scheduling logic only
+talks to the Executor interface below.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+from typing import Callable, Protocol
+
+import numpy as np
+
+ELEM_BYTES = {"uint32": 4, "float32": 4, "int64": 8}
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    arrival: float  # seconds after the start of the run
+    n: int
+    dtype: str
+    seed: int
+
+    @property
+    def elem_bytes(self) -> int:
+        return ELEM_BYTES[self.dtype]
+
+    @property
+    def out_bytes(self) -> int:
+        return self.n * self.elem_bytes
+
+
+@dataclasses.dataclass
+class Completion:
+    request: Request
+    admitted: float
+    done: float
+    batch_size: int
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.request.arrival
+
+
+class Executor(Protocol):
+    """Device side of the server.  A launch covers one or more requests of
+    one element size; `poll` returns True once its results are final."""
+
+    def place(self, req: Request) -> None: ...
+    def launch(self, reqs: list[Request]) -> object: ...
+    def poll(self, handle: object) -> bool: ...
+    def results(self, handle: object) -> dict[int, object]: ...
+    def release(self, handle: object) -> None: ...
+
+
+@dataclasses.dataclass
+class ServeReport:
+    completions: list[Completion]
+    wall_s: float
+    launches: int
+    batched_launches: int
+    max_reserved_bytes: int
+    budget_bytes: int
+
+    def ok(self) -> list[Completion]:
+        return [c for c in self.completions if c.error is None]
+
+    def summary(self) -> dict:
+        ok = self.ok()
+        lat = np.array([c.latency for c in ok]) if ok else np.zeros(1)
+        items = sum(c.request.n for c in ok)
+        return {
+            "requests": len(self.completions),
+            "completed": len(ok),
+            "failed": len(self.completions) - len(ok),
+            "wall_s": self.wall_s,
+            "requests_per_s": len(ok) / self.wall_s if self.wall_s > 0 else math.nan,
+            "Gelem_per_s": items / self.wall_s / 1e9 if self.wall_s > 0 else math.nan,
+            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "latency_p90_ms": float(np.percentile(lat, 90) * 1e3),
+            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "latency_max_ms": float(lat.max() * 1e3),
+            "launches": self.launches,
+            "batched_launches": self.batched_launches,
+            "mean_requests_per_launch": len(self.completions) / max(self.launches, 1),
+            "max_reserved_bytes": self.max_reserved_bytes,
+            "budget_bytes": self.budget_bytes,
+        }
+
+
+class ShuffleServer:
+    def __init__(self, executor: Executor, budget_bytes: int, small_items: int = 1 << 20,
+                 max_batch_requests: int = 2048, max_batch_items: int = 1 << 26, max_inflight: int = 16,
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.small_items = small_items
+        self.max_batch_requests = max_batch_requests
+        self.max_batch_items = max_batch_items
+        self.max_inflight = max_inflight
+        self.clock = clock
+        self.sleep = sleep
+        self.cancelled: set[int] = set()
+
+    def cancel(self, request_id: int) -> None:
+        """Drop a request that has not been admitted yet."""
+        self.cancelled.add(request_id)
+
+    def _groups(self, ready: list[Request]) -> list[list[Request]]:
+        """Split admitted requests into launches: big ones alone, small ones
+        coalesced per element size (in admission order)."""
+        groups: list[list[Request]] = []
+        small: dict[int, list[Request]] = {}
+        for r in ready:
+            if r.n > self.small_items:
+                groups.append([r])
+                continue
+            cur = small.setdefault(r.elem_bytes, [])
+            if cur and (len(cur) >= self.max_batch_requests or
+                        sum(q.n for q in cur) + r.n > self.max_batch_items):
+                groups.append(cur)
+                cur = small[r.elem_bytes] = []
+            cur.append(r)
+        groups.extend(g for g in small.values() if g)
+        return groups
+
+    def run(self, requests: list[Request], on_result: Callable[[Request, object], None] | None = None) -> ServeReport:
+        pending = deque(sorted(requests, key=lambda r: (r.arrival, r.id)))
+        admitted: list[Request] = []
+        admit_time: dict[int, float] = {}
+        inflight: list[tuple[object, list[Request]]] = []
+        completions: list[Completion] = []
+        reserved = max_reserved = 0
+        launches = batched = 0
+        t0 = self.clock()
+        while pending or admitted or inflight:
+            now = self.clock() - t0
+            # retire finished launches
+            still = []
+            for handle, reqs in inflight:
+                try:
+                    finished = self.ex.poll(handle)
+                except Exception as exc:  # a failed launch fails only its own requests
+                    finished, err = True, f"{type(exc).__name__}: {exc}"
+                else:
+                    err = None
+                if not finished:
+                    still.append((handle, reqs))
+                    continue
+                t_done = self.clock() - t0
+                outs = {}
+                if err is None:
+                    try:
+                        outs = self.ex.results(handle)
+                    except Exception as exc:
+                        err = f"{type(exc).__name__}: {exc}"
+                for r in reqs:
+                    completions.append(Completion(r, admit_time[r.id], t_done, len(reqs), err))
+                    if err is None and on_result is not None:
+                        on_result(r, outs[r.id])
+                    reserved -= r.out_bytes
+                self.ex.release(handle)
+            inflight = still
+            # admit arrived requests while the budget allows (FIFO)
+            while pending and pending[0].arrival <= now:
+                r = pending[0]
+                if r.id in self.cancelled:
+                    pending.popleft()
+                    continue
+                if r.out_bytes > self.budget:
+                    pending.popleft()
+                    completions.append(Completion(r, now, now, 0, "request exceeds the HBM budget"))
+                    continue
+                if reserved + r.out_bytes > self.budget:
+                    break
+                pending.popleft()
+                reserved += r.out_bytes
+                max_reserved = max(max_reserved, reserved)
+                admit_time[r.id] = now
+                try:
+                    self.ex.place(r)
+                except Exception as exc:
+                    reserved -= r.out_bytes
+                    completions.append(Completion(r, now, self.clock() - t0, 0, f"{type(exc).__name__}: {exc}"))
+                    continue
+                admitted.append(r)
+            # launch what is admitted, as slots allow
+            if admitted and len(inflight) < self.max_inflight:
+                groups = self._groups(admitted)
+                admitted = []
+                for g in groups:
+                    if len(inflight) >= self.max_inflight:
+                        admitted.extend(g)
+                        continue
+                    try:
+                        handle = self.ex.launch(g)
+                    except Exception as exc:
+                        t_fail = self.clock() - t0
+                        for r in g:
+                            completions.append(Completion(r, admit_time[r.id], t_fail, len(g),
+                                                          f"{type(exc).__name__}: {exc}"))
+                            reserved -= r.out_bytes
+                        continue
+                    inflight.append((handle, g))
+                    launches += 1
+                    batched += len(g) > 1
+            if not inflight and not admitted and pending:
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0:
+                    self.sleep(min(wait, 0.001))
+            elif inflight:
+                self.sleep(0)
+        wall = self.clock() - t0
+        return ServeReport(completions, wall, launches, batched, max_reserved, self.budget)
+
+
+# ------------------------------------------------------------ HIP executor --
+class HipExecutor:
+    """Runs launches with libbshuffle on one GPU.
+
+    Inputs live in device-resident pools (one per element size) filled once
+    with seeded random bytes; a request's input is the next `n` records of
+    its pool, assigned in admission order, so consecutive small requests of
+    one element size are contiguous and one bs_shuffle_batched covers them.
+    Outputs are allocated per launch and returned as views.
+    """
+
+    def __init__(self, device="cuda:0", streams: int = 4, rounds: int = 24, pool_items: int = 1 << 27,
+                 pool_seed: int = 2106):
+        import torch
+
+        import paper_2106_06161_amd as bs
+
+        self.torch, self.bs = torch, bs
+        self.device = torch.device(device)
+        self.rounds = rounds
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(streams)]
+        self.next_stream = 0
+        gen = torch.Generator(device=self.device)
+        gen.manual_seed(pool_seed)
+        self.pools = {
+            4: torch.randint(-2**31, 2**31 - 1, (pool_items,), dtype=torch.int32, device=self.device, generator=gen),
+            8: torch.randint(-2**63, 2**63 - 1, (pool_items,), dtype=torch.int64, device=self.device, generator=gen),
+        }
+        self.cursor = {4: 0, 8: 0}
+        self.where: dict[int, tuple[int, int]] = {}  # request id -> (elem_bytes, first record in its pool)
+        torch.cuda.synchronize(self.device)
+
+    def place(self, req: Request) -> None:
+        eb = req.elem_bytes
+        pool = self.pools[eb]
+        if req.n > pool.numel():
+            raise ValueError(f"request of {req.n} records exceeds the input pool")
+        if self.cursor[eb] + req.n > pool.numel():
+            self.cursor[eb] = 0
+        self.where[req.id] = (eb, self.cursor[eb])
+        self.cursor[eb] += req.n
+
+    def input_of(self, req: Request):
+        eb, first = self.where[req.id]
+        return self.pools[eb][first:first + req.n]
+
+    def launch(self, reqs: list[Request]):
+        torch, bs = self.torch, self.bs
+        stream = self.streams[self.next_stream]
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        eb = reqs[0].elem_bytes
+        firsts = [self.where[r.id][1] for r in reqs]
+        contiguous = all(firsts[i] + reqs[i].n == firsts[i + 1] for i in range(len(reqs) - 1))
+        with torch.cuda.stream(stream):
+            if len(reqs) == 1:
+                x = self.input_of(reqs[0])
+                y = bs.shuffle(x, reqs[0].seed, self.rounds)
+                outs = {reqs[0].id: y}
+                keep = ()
+            elif contiguous:
+                total = sum(r.n for r in reqs)
+                x = self.pools[eb][firsts[0]:firsts[0] + total]
+                offs = np.zeros(len(reqs) + 1, dtype=np.int64)
+                np.cumsum([r.n for r in reqs], out=offs[1:])
+                seeds = np.array([r.seed & (2**64 - 1) for r in reqs], dtype=np.uint64).view(np.int64)
+                off_h = torch.from_numpy(offs).pin_memory()
+                sd_h = torch.from_numpy(seeds).pin_memory()
+                off_d = off_h.to(self.device, non_blocking=True)
+                sd_d = sd_h.to(self.device, non_blocking=True)
+                y = bs.shuffle_batched(x, off_d, sd_d, self.rounds)
+                outs = {r.id: y[int(offs[i]):int(offs[i + 1])] for i, r in enumerate(reqs)}
+                keep = (off_h, sd_h, off_d, sd_d)
+            else:  # a pool wrap split the run: fall back to one launch per request
+                outs = {r.id: bs.shuffle(self.input_of(r), r.seed, self.rounds) for r in reqs}
+                keep = ()
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return {"event": ev, "outs": outs, "keep": keep, "stream": stream}
+
+    def poll(self, handle) -> bool:
+        return handle["event"].query()
+
+    def results(self, handle) -> dict[int, object]:
+        return handle["outs"]
+
+    def release(self, handle) -> None:
+        handle["outs"] = None
+        handle["keep"] = None
+
+    def check_errors(self) -> int:
+        for s in self.streams:
+            err = self.bs.workspace_error(stream=s, device=self.device)
+            if err:
+                return err
+        return 0
+
+
+def make_requests(count: int, lo: int, hi: int, qps: float, seed: int) -> list[Request]:
+    """Poisson arrivals at `qps`, log-uniform sizes in [lo, hi], dtype uniform
+    over uint32 / int64 / float32, 64-bit seeds (PCG64(seed))."""
+    from .workloads import request_stream
+
+    return [Request(d["id"], d["arrival"], d["n"], d["dtype"], d["seed"])
+            for d in request_stream(count, lo, hi, qps, seed)]
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+
+    p = argparse.ArgumentParser(description="Run the shuffle server on a synthetic request stream.")
+    p.add_argument("--requests", type=int, default=2000)
+    p.add_argument("--lo", type=int, default=1000)
+    p.add_argument("--hi", type=int, default=100_000_000)
+    p.add_argument("--qps", type=float, default=0.0, help="0: measure closed-loop capacity first, run at 0.8x")
+    p.add_argument("--budget-gib", type=float, default=32.0)
+    p.add_argument("--streams", type=int, default=4)
+    p.add_argument("--rounds", type=int, default=24)
+    p.add_argument("--seed", type=int, default=5)
+    a = p.parse_args(argv)
+    ex = HipExecutor(streams=a.streams, rounds=a.rounds)
+    server = ShuffleServer(ex, int(a.budget_gib * 2**30))
+    qps = a.qps
+    out = {}
+    if qps <= 0:
+        cap = server.run(make_requests(a.requests, a.lo, a.hi, 1e12, a.seed)).summary()
+        out["closed_loop"] = cap
+        qps = 0.8 * cap["requests_per_s"]
+    rep = server.run(make_requests(a.requests, a.lo, a.hi, qps, a.seed + 1))
+    out["open_loop"] = dict(rep.summary(), qps=qps)
+    out["device_error"] = ex.check_errors()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
