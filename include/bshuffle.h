@@ -151,13 +151,26 @@ bs_status bs_shuffle_batched(const void *in, void *out, const int64_t *offsets,
  * (16,16,1) (16,8,1) (8,8,2) (4,16,1).  grid_mult: 0 = a persistent grid of
  * as many workgroups as the device keeps resident, 1..64 = that many
  * workgroups per CU, BS_GRID_ONE_PER_TILE = one workgroup per tile.
- * bs_set_config(0, 0, 0, 0) restores the default.  Applies to later calls
- * from every thread; returns BS_EINVAL for a shape that is not compiled.
+ * bs_set_config with a shape forces it for every later call (from every
+ * thread), ignoring the tuned table; bs_set_config(0, 0, 0, 0) restores the
+ * default and re-enables the tuned table.  BS_EINVAL for a shape that is not
+ * compiled.
  */
 #define BS_GRID_ONE_PER_TILE 1000u
 bs_status bs_set_config(uint32_t waves_per_group, uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
 bs_status bs_get_config(uint32_t *waves_per_group, uint32_t *items_per_lane, uint32_t *depth,
                         uint32_t *grid_mult);
+
+/*
+ * Tuned launch shapes (filled by the project's autotuner; never change results).
+ * kind 0 = bs_shuffle, keyed by the domain bits k of the call; kind 1 =
+ * bs_shuffle_batched, keyed by ceil(log2(mean segment size)).  A call uses the
+ * entry for (kind, elem_bytes, size class) when there is one and no shape was
+ * forced with bs_set_config; otherwise the default shape.
+ */
+bs_status bs_set_tuned_config(uint32_t kind, uint32_t elem_bytes, uint32_t size_bits, uint32_t waves_per_group,
+                              uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
+bs_status bs_clear_tuned_configs(void);
 
 #ifdef __cplusplus
 }

@@ -47,6 +47,8 @@ _SIGNATURES = {
     "bs_shuffle_batched": (_i32, [_vp, _vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp, _sz, _vp]),
     "bs_set_config": (_i32, [_u32, _u32, _u32, _u32]),
     "bs_get_config": (_i32, [_vp, _vp, _vp, _vp]),
+    "bs_set_tuned_config": (_i32, [_u32, _u32, _u32, _u32, _u32, _u32, _u32]),
+    "bs_clear_tuned_configs": (_i32, []),
     "bs_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
@@ -69,6 +71,10 @@ def lib() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = l
+        # launch shapes picked by the autotuner (speed only; results never depend on them)
+        from . import autotune
+
+        autotune.apply(autotune.load())
     return _lib
 
 
@@ -137,6 +143,15 @@ def bs_get_config() -> tuple[int, int, int, int]:
     w, i, d, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
     _check(lib().bs_get_config(ctypes.byref(w), ctypes.byref(i), ctypes.byref(d), ctypes.byref(g)), "bs_get_config")
     return w.value, i.value, d.value, g.value
+
+
+def bs_set_tuned_config(kind: int, elem_bytes: int, size_bits: int, waves: int, items: int, depth: int,
+                        grid_mult: int) -> int:
+    return int(lib().bs_set_tuned_config(kind, elem_bytes, size_bits, waves, items, depth, grid_mult))
+
+
+def bs_clear_tuned_configs() -> int:
+    return int(lib().bs_clear_tuned_configs())
 
 
 def bs_probe_copy(in_ptr, out_ptr, nbytes, stream) -> int:

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "bshuffle.h"
@@ -29,6 +30,18 @@ constexpr size_t kHeaderBytes = sizeof(bsd::WorkspaceHeader);
 std::mutex g_mu;
 bsd::LaunchConfig g_default_cfg = {16, 16, 1, 0};
 bsd::LaunchConfig g_cfg = g_default_cfg;
+bool g_forced = false;  // bs_set_config with a shape: ignore the tuned table
+
+// Tuned launch shapes keyed by (call kind, element bytes, size class).
+// Single calls use the domain bits k; batched calls the bits of the mean
+// segment size.
+std::map<std::tuple<uint32_t, uint32_t, uint32_t>, bsd::LaunchConfig> g_tuned;
+
+bsd::LaunchConfig pick_config(uint32_t kind, uint32_t elem_bytes, uint32_t bits) {
+  if (g_forced) return g_cfg;
+  auto it = g_tuned.find(std::make_tuple(kind, elem_bytes, bits));
+  return it != g_tuned.end() ? it->second : g_cfg;
+}
 bool g_nontemporal_store = false;
 
 struct CacheEntry {
@@ -223,11 +236,29 @@ bs_status bs_set_config(uint32_t waves, uint32_t items, uint32_t depth, uint32_t
   std::lock_guard<std::mutex> lock(g_mu);
   if (waves == 0 && items == 0 && depth == 0 && grid_mult == 0) {
     g_cfg = g_default_cfg;
+    g_forced = false;
     return BS_OK;
   }
   bsd::LaunchConfig c = {waves, items, depth, grid_mult};
   if (!bsd::config_supported(c) || (grid_mult > 64 && grid_mult != bsd::kGridOnePerTile)) return BS_EINVAL;
   g_cfg = c;
+  g_forced = true;
+  return BS_OK;
+}
+
+bs_status bs_set_tuned_config(uint32_t kind, uint32_t elem_bytes, uint32_t size_bits, uint32_t waves,
+                              uint32_t items, uint32_t depth, uint32_t grid_mult) {
+  if (kind > 1 || !valid_elem_bytes(elem_bytes) || size_bits > 40) return BS_EINVAL;
+  bsd::LaunchConfig c = {waves, items, depth, grid_mult};
+  if (!bsd::config_supported(c) || (grid_mult > 64 && grid_mult != bsd::kGridOnePerTile)) return BS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tuned[std::make_tuple(kind, elem_bytes, size_bits)] = c;
+  return BS_OK;
+}
+
+bs_status bs_clear_tuned_configs(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tuned.clear();
   return BS_OK;
 }
 
@@ -268,7 +299,7 @@ bs_status bs_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes,
   a.key[rounds] = 0;
 
   std::lock_guard<std::mutex> lock(g_mu);
-  const bsd::LaunchConfig cfg = g_cfg;
+  const bsd::LaunchConfig cfg = pick_config(0, elem_bytes, k);
   const bool wide = k > 32;
   const uint64_t tile = wide ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;
   a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
@@ -305,7 +336,8 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
   if (lay.capacity > 0xFFFFFFFFull) return BS_EINVAL;
 
   std::lock_guard<std::mutex> lock(g_mu);
-  const bsd::LaunchConfig cfg = g_cfg;
+  const bsd::LaunchConfig cfg =
+      pick_config(1, elem_bytes, ceil_log2((total_items + num_segments - 1) / num_segments));
   void* ws = nullptr;
   bs_status st = resolve_workspace(workspace, workspace_bytes, lay.total, s, &ws);
   if (st != BS_OK) return st;

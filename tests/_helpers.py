@@ -30,3 +30,27 @@ def oracle_window(x: np.ndarray, seed: int, rounds: int, i_begin: int, i_end: in
     n = x.shape[0]
     rank = kept_before(n, seed, rounds, i_begin)
     return rank, oracle.shuffle_window(x, seed, rounds, i_begin, i_end)
+
+
+def kept_before_fast(n: int, seed: int, rounds: int, i: int) -> int:
+    """Same as kept_before, counting from whichever end of the domain is nearer."""
+    domain = 1 << oracle.domain_bits(n)
+    if i > domain // 2:
+        rest = domain - i
+        chunks = max(1, min(THREADS * 4, rest // 65536))
+        bounds = np.linspace(i, domain, chunks + 1, dtype=np.int64)
+        with concurrent.futures.ThreadPoolExecutor(THREADS) as ex:
+            parts = ex.map(lambda ab: oracle.count_kept(n, seed, rounds, int(ab[0]), int(ab[1])),
+                           zip(bounds[:-1], bounds[1:]))
+            return n - int(sum(parts))
+    return kept_before(n, seed, rounds, i)
+
+
+def check_slices(x_np: np.ndarray, y_np: np.ndarray, seed: int, rounds: int, starts, span: int = 1 << 20):
+    """Compares the GPU output y with the oracle on padded-index slices."""
+    n = x_np.shape[0]
+    for s in starts:
+        rank = kept_before_fast(n, seed, rounds, s)
+        want = oracle.shuffle_window(x_np, seed, rounds, s, s + span)
+        got = y_np[rank:rank + len(want)]
+        assert np.array_equal(got, want), (n, s)

@@ -105,3 +105,25 @@ def test_probe_argument_checks():
     assert B.bs_probe_copy(FAKE_IN, FAKE_IN + 16, 64, None) == B.BS_EALIAS
     assert B.bs_probe_gather(FAKE_IN, 10, FAKE_OUT, None, 10, 4, None) == B.BS_EINVAL
     assert B.bs_probe_cipher_scan(10, 1, 99, None, 0, None) == B.BS_EINVAL
+
+
+def test_tuned_config_table():
+    assert B.bs_set_tuned_config(0, 4, 28, 16, 16, 1, 0) == B.BS_OK
+    assert B.bs_set_tuned_config(1, 8, 12, 8, 16, 2, 1) == B.BS_OK
+    assert B.bs_set_tuned_config(2, 4, 28, 16, 16, 1, 0) == B.BS_EINVAL  # kind
+    assert B.bs_set_tuned_config(0, 3, 28, 16, 16, 1, 0) == B.BS_EINVAL  # element size
+    assert B.bs_set_tuned_config(0, 4, 41, 16, 16, 1, 0) == B.BS_EINVAL  # size class
+    assert B.bs_set_tuned_config(0, 4, 28, 16, 4, 1, 0) == B.BS_EINVAL   # shape not compiled
+    assert B.bs_clear_tuned_configs() == B.BS_OK
+    from paper_2106_06161_amd import autotune
+
+    autotune.apply(autotune.load())
+
+
+def test_shipped_tuned_table_is_valid():
+    from paper_2106_06161_amd import autotune
+
+    entries = autotune.load()
+    for e in entries:
+        assert (e["waves"], e["items"], e["depth"]) in [tuple(s) for s in autotune.SHAPES]
+    assert autotune.apply(entries) == len(entries)

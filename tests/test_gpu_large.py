@@ -1,0 +1,69 @@
+"""Full-size single shuffles: 10^9 uint32 records, 2.5*10^8 records of 16
+bytes, and a domain past 2^32 (64-bit index path).  Checked on oracle slices
+at the start, middle and end of the padded domain, and by properties that
+hold at any size (the output is a permutation of the input)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2106_06161_amd as bs
+from paper_2106_06161_amd import workloads as W
+from _helpers import check_slices
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def test_billion_uint32_arange():
+    n, seed, rounds = 10**9, 1, 24
+    x = torch.arange(n, dtype=torch.int64, device=DEV).to(torch.int32)
+    y = bs.shuffle(x, seed, rounds)
+    torch.cuda.synchronize()
+    assert bs.workspace_error() == 0
+    assert torch.equal(torch.sort(y)[0], x)  # a permutation of arange(n)
+    del x
+    y_np = y.cpu().numpy().view(np.uint32)
+    x_np = np.arange(n, dtype=np.uint32)
+    domain = 1 << oracle.domain_bits(n)
+    check_slices(x_np, y_np, seed, rounds, [0, domain - (1 << 20)])
+
+
+def test_16_byte_records():
+    n, seed, rounds = 250_000_000, 11, 24
+    x_np = W.normal_records_f32(n, 4, seed=11)
+    x = torch.from_numpy(x_np).to(DEV)
+    y = bs.shuffle(x, seed, rounds)
+    torch.cuda.synchronize()
+    assert bs.workspace_error() == 0
+    # same multiset of records: two order-independent checksums over the 4 words
+    xi, yi = x.view(torch.int32).to(torch.int64), y.view(torch.int32).to(torch.int64)
+    for w in (torch.tensor([1, 3, 5, 7], device=DEV), torch.tensor([11, -13, 17, 19], device=DEV)):
+        assert torch.equal((xi * w).sum(dim=1).sum(), (yi * w).sum(dim=1).sum())
+    del x, xi, yi
+    y_np = y.cpu().numpy()
+    domain = 1 << oracle.domain_bits(n)
+    check_slices(x_np, y_np, seed, rounds, [0, domain // 2, domain - (1 << 20)], span=1 << 19)
+
+
+def test_domain_beyond_32_bits():
+    """n = 2^32 + 1 one-byte records: k = 33, 64-bit indices."""
+    n, seed, rounds = (1 << 32) + 1, 3, 4
+    x_np = W.random_bytes(n, seed=3)
+    x = torch.from_numpy(x_np).to(DEV)
+    y = bs.shuffle(x, seed, rounds)
+    torch.cuda.synchronize()
+    assert bs.workspace_error() == 0
+    def histogram(t):
+        h = torch.zeros(256, dtype=torch.int64, device=DEV)
+        for c in torch.split(t, 1 << 28):
+            h += torch.bincount(c.to(torch.int32), minlength=256)
+        return h
+
+    assert torch.equal(histogram(x), histogram(y))
+    del x
+    y_np = y.cpu().numpy()
+    domain = 1 << oracle.domain_bits(n)
+    assert domain == 1 << 33
+    check_slices(x_np, y_np, seed, rounds, [0, domain - (1 << 20)])
