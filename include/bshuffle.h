@@ -172,6 +172,12 @@ bs_status bs_set_tuned_config(uint32_t kind, uint32_t elem_bytes, uint32_t size_
                               uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
 bs_status bs_clear_tuned_configs(void);
 
+/* The launch shape a call would use: kind 0 = bs_shuffle of `items` records,
+ * kind 1 = bs_shuffle_batched of `items` records in num_segments segments. */
+bs_status bs_query_config(uint32_t kind, uint32_t elem_bytes, uint64_t items, uint32_t num_segments,
+                          uint32_t *waves_per_group, uint32_t *items_per_lane, uint32_t *depth,
+                          uint32_t *grid_mult);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vphilox_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_STD_SRC = os.path.join(_HERE, "std_shuffle.cpp")
+_STD_LIB = os.path.join(_HERE, "libstdshuffle.so")
 
 MAX_ROUNDS = 64
 MIN_DOMAIN_BITS = 4
@@ -33,6 +35,10 @@ def build(force: bool = False) -> str:
             ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp]
         )
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_STD_LIB) or os.path.getmtime(_STD_LIB) < os.path.getmtime(_STD_SRC):
+        tmp = _STD_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", _STD_SRC, "-o", tmp])
+        os.replace(tmp, _STD_LIB)
     return _LIB
 
 
@@ -235,3 +241,16 @@ def pair_discordances(perms: np.ndarray) -> np.ndarray:
     if _load().orc_pair_discordances(_ptr(perms), p, n, _ptr(out)) != 0:
         raise ValueError("rows must be permutations")
     return out[: p // 2]
+
+
+# ------------------------------------------------------- CPU timing reference --
+def std_shuffle_u32(x: np.ndarray, seed: int) -> np.ndarray:
+    """std::shuffle with std::mt19937_64(seed) on a copy of x (uint32), single thread.
+    A timing reference for the benchmark, not a reference for the method."""
+    build()
+    lib = ctypes.CDLL(_STD_LIB)
+    lib.cpu_std_shuffle_u32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]
+    lib.cpu_std_shuffle_u32.restype = None
+    y = np.array(x, dtype=np.uint32, copy=True)
+    lib.cpu_std_shuffle_u32(_ptr(y), len(y), seed & (2**64 - 1))
+    return y

@@ -49,6 +49,7 @@ _SIGNATURES = {
     "bs_get_config": (_i32, [_vp, _vp, _vp, _vp]),
     "bs_set_tuned_config": (_i32, [_u32, _u32, _u32, _u32, _u32, _u32, _u32]),
     "bs_clear_tuned_configs": (_i32, []),
+    "bs_query_config": (_i32, [_u32, _u32, _u64, _u32, _vp, _vp, _vp, _vp]),
     "bs_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
@@ -148,6 +149,13 @@ def bs_get_config() -> tuple[int, int, int, int]:
 def bs_set_tuned_config(kind: int, elem_bytes: int, size_bits: int, waves: int, items: int, depth: int,
                         grid_mult: int) -> int:
     return int(lib().bs_set_tuned_config(kind, elem_bytes, size_bits, waves, items, depth, grid_mult))
+
+
+def bs_query_config(kind: int, elem_bytes: int, items: int, num_segments: int = 0) -> tuple[int, int, int, int]:
+    w, i, d, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().bs_query_config(kind, elem_bytes, items, num_segments, ctypes.byref(w), ctypes.byref(i),
+                                 ctypes.byref(d), ctypes.byref(g)), "bs_query_config")
+    return w.value, i.value, d.value, g.value
 
 
 def bs_clear_tuned_configs() -> int:

@@ -256,6 +256,22 @@ bs_status bs_set_tuned_config(uint32_t kind, uint32_t elem_bytes, uint32_t size_
   return BS_OK;
 }
 
+bs_status bs_query_config(uint32_t kind, uint32_t elem_bytes, uint64_t items, uint32_t num_segments,
+                          uint32_t* waves, uint32_t* items_per_lane, uint32_t* depth, uint32_t* grid_mult) {
+  if (kind > 1 || !valid_elem_bytes(elem_bytes) || !waves || !items_per_lane || !depth || !grid_mult)
+    return BS_EINVAL;
+  if (kind == 1 && num_segments == 0) return BS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const uint32_t bits = kind == 0 ? bs_domain_bits(items) : ceil_log2((items + num_segments - 1) / num_segments);
+  bsd::LaunchConfig c = pick_config(kind, elem_bytes, bits);
+  if (kind == 0 && bits > 32) c = {bsd::kWideWaves, bsd::kWideItems, 1, c.grid_mult};
+  *waves = c.waves;
+  *items_per_lane = c.items;
+  *depth = c.depth;
+  *grid_mult = c.grid_mult;
+  return BS_OK;
+}
+
 bs_status bs_clear_tuned_configs(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_tuned.clear();

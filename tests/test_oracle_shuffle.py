@@ -116,3 +116,10 @@ def test_golden_outputs_unchanged():
         out = oracle.shuffle(np.arange(n, dtype=np.uint32), seed, rounds)
         assert hashlib.sha256(out.tobytes()).hexdigest() == case["sha256"], case
         assert out[: len(case["head"])].tolist() == case["head"], case
+
+
+def test_std_shuffle_reference_is_a_permutation():
+    x = np.arange(10_000, dtype=np.uint32)
+    y = oracle.std_shuffle_u32(x, 7)
+    assert np.array_equal(np.sort(y), x) and not np.array_equal(y, x)
+    assert np.array_equal(y, oracle.std_shuffle_u32(x, 7))
