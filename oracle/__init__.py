@@ -91,6 +91,10 @@ def _load():
         lib.orc_discordant_pairs.restype = i64
         lib.orc_pair_discordances.argtypes = [vp, u64, u32, vp]
         lib.orc_pair_discordances.restype = ctypes.c_int
+        lib.orc_lcg_params.argtypes = [u64, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        lib.orc_lcg_params.restype = None
+        lib.orc_lcg_shuffle.argtypes = [vp, vp, u64, u32, u64]
+        lib.orc_lcg_shuffle.restype = i64
         _lib = lib
     return _lib
 
@@ -218,6 +222,27 @@ def permutations(n: int, seeds, rounds: int) -> np.ndarray:
     x = np.tile(np.arange(n, dtype=np.uint32), p)
     offsets = np.arange(p + 1, dtype=np.int64) * n
     return shuffle_batched(x, offsets, seeds, rounds).reshape(p, n)
+
+
+def lcg_params(n: int, seed: int) -> tuple[int, int]:
+    a, c = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().orc_lcg_params(n, seed & (2**64 - 1), ctypes.byref(a), ctypes.byref(c))
+    return a.value, c.value
+
+
+def lcg_shuffle(x: np.ndarray, seed: int) -> np.ndarray:
+    """Algorithm 1 with the LCG bijection y = (a*i + c) mod 2^k (Sec. 3.1)."""
+    x, eb = _as_bytes(x)
+    out = np.empty_like(x)
+    n = x.shape[0]
+    got = _load().orc_lcg_shuffle(_ptr(x), _ptr(out), n, eb, seed & (2**64 - 1))
+    if got != n:
+        raise ValueError(f"oracle LCG shuffle failed ({got})")
+    return out
+
+
+def lcg_permutations(n: int, seeds) -> np.ndarray:
+    return np.stack([lcg_shuffle(np.arange(n, dtype=np.uint32), int(s)) for s in seeds])
 
 
 # ------------------------------------------------------ Mallows helpers --

@@ -39,6 +39,9 @@
  *    the next free output slot.  The running count is the exclusive scan of
  *    the flags, so out[rank(i)] = in[f(i)].
  *
+ * The linear congruential bijection of Sec. 3.1, y = (a*x + c) mod 2^k with a
+ * odd, and Algorithm 1 run with it (the paper's low-quality comparison).
+ *
  * Mallows-kernel helpers (Sec. 5): the number of discordant pairs n_dis of
  * two permutations, by brute force over all pairs and by merge-sort
  * inversion counting.
@@ -383,4 +386,39 @@ int orc_pair_discordances(const uint32_t *perms, uint64_t num_perms, uint32_t n,
     out[p / 2] = (uint64_t)d;
   }
   return ORC_OK;
+}
+
+/* ------------------------------------------------------------ LCG bijection -- */
+
+/* The linear congruential bijection of Sec. 3.1: y = (a*x + c) mod 2^k with
+ * a odd (coprime to the power-of-two modulus).  Keyed from the seed: a is the
+ * first SplitMix64 output forced odd, c the second, both reduced mod 2^k. */
+void orc_lcg_params(uint64_t n, uint64_t seed, uint64_t *a, uint64_t *c) {
+  uint64_t st = seed;
+  const uint32_t k = orc_domain_bits(n);
+  const uint64_t mask = (k >= 64) ? ~(uint64_t)0 : (((uint64_t)1 << k) - 1);
+  *a = (orc_splitmix64_next(&st) | 1u) & mask;
+  *c = orc_splitmix64_next(&st) & mask;
+}
+
+/* Algorithm 1 with the LCG as the bijection: for i in increasing order, keep
+ * y = (a*i + c) mod 2^k when y < n. */
+int64_t orc_lcg_shuffle(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed) {
+  uint64_t a, c, i, size, mask, j = 0;
+  uint32_t k;
+  if (check_shuffle_args(n, elem_bytes, 0) != ORC_OK) return ORC_EINVAL;
+  if (n == 0) return 0;
+  if (!in || !out) return ORC_EINVAL;
+  k = orc_domain_bits(n);
+  size = (uint64_t)1 << k;
+  mask = size - 1;
+  orc_lcg_params(n, seed, &a, &c);
+  for (i = 0; i < size; i++) {
+    uint64_t y = (a * i + c) & mask;
+    if (y < n) {
+      memcpy((uint8_t *)out + j * elem_bytes, (const uint8_t *)in + y * elem_bytes, elem_bytes);
+      j++;
+    }
+  }
+  return (int64_t)j;
 }
