@@ -17,6 +17,10 @@ Prints ONE JSON line:
   cpu_baseline the sequential CPU oracle on a bounded sample (one thread)
   ceilings     measured device copy and random-gather rates, the cipher+scan
                kernel alone, the 4-round and power-of-two variants
+  fusion       the fused kernel against the less-fused forms of Sec. 6
+               (Bijective0: cipher table, compaction, gather as three passes;
+               Bijective1: a separate tile-count and scan pass before the
+               gather) and the LCG bijection in the same fused kernel
   batched      4,096 independent shuffles in one launch vs 4,096 calls
   serving      the continuous-batching server: capacity, p50 / p99 latency
 
@@ -70,6 +74,9 @@ def parse_args():
     p.add_argument("--rounds", type=int, default=ROUNDS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-ceilings", action="store_true")
+    p.add_argument("--no-fusion", action="store_true")
+    p.add_argument("--fusion-sweep", action="store_true",
+                   help="also time every fusion form over n = 2^20 .. 2^29 (+1)")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serve-requests", type=int, default=2000)
@@ -211,6 +218,53 @@ def bench_batched(torch, bs, W, np, dev, stream, timer, rounds) -> dict:
     }
 
 
+def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None, ws=None) -> dict:
+    """One shuffle of n uint32 values in each fusion form; every form's output
+    is checked equal to the fused kernel's."""
+    sp = stream.cuda_stream
+    if x is None:
+        x = torch.from_numpy(W.uniform_u32(n, seed=SEED)).to(dev)
+        y = torch.empty_like(x)
+        ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+    ref = torch.empty_like(x)
+    scratch = torch.empty(B.bs_probe_unfused_scratch_bytes(n), dtype=torch.uint8, device=dev)
+
+    def fused():
+        bs.shuffle(x, SEED, rounds, out=y, workspace=ws)
+
+    def two_pass():
+        B._check(B.bs_probe_shuffle_two_pass(x.data_ptr(), y.data_ptr(), n, 4, SEED, rounds, ws.data_ptr(),
+                                             ws.numel(), sp), "bs_probe_shuffle_two_pass")
+
+    def unfused():
+        B._check(B.bs_probe_shuffle_unfused(x.data_ptr(), y.data_ptr(), n, 4, SEED, rounds, scratch.data_ptr(),
+                                            scratch.numel(), ws.data_ptr(), ws.numel(), sp),
+                 "bs_probe_shuffle_unfused")
+
+    def lcg():
+        bs.shuffle_lcg(x, SEED, out=y, workspace=ws)
+
+    bs.shuffle(x, SEED, rounds, out=ref, workspace=ws)
+    res = {"n": n}
+    for name, fn in (("bijective2_fused", fused), ("bijective1_two_pass", two_pass),
+                     ("bijective0_unfused", unfused)):
+        t = timer.run(fn, 5)
+        res[name + "_ms"] = t * 1e3
+        res[name + "_Gelem_s"] = n / t / 1e9
+        if not torch.equal(y, ref):
+            raise RuntimeError(f"fusion form {name} differs from the fused kernel at n={n}")
+    t = timer.run(lcg, 5)
+    res["lcg_fused_ms"] = t * 1e3
+    res["lcg_fused_Gelem_s"] = n / t / 1e9
+    perm = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
+    t = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), n, y.data_ptr(), perm.data_ptr(), n, 4, sp), 5)
+    res["gather_index_array_ms"] = t * 1e3
+    del perm, scratch
+    if bs.workspace_error(ws) != 0:
+        raise RuntimeError("device-side error in the fusion forms")
+    return res
+
+
 def bench_serving(rounds: int, count: int) -> dict:
     """The continuous-batching server: closed-loop capacity (every request
     arrives at once), then Poisson arrivals at 0.8x that rate."""
@@ -238,7 +292,7 @@ def main() -> int:
     args = parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the shuffle is single-device; see the sharding notes in DESIGN.md)", flush=True)
+              "(the shuffle runs on a single device)", flush=True)
         return 2
     import numpy as np
     import torch
@@ -363,6 +417,17 @@ def main() -> int:
         if bs.workspace_error(ws) != 0:
             log("bench: device-side error in ceilings")
             return 1
+
+    if not args.no_fusion:
+        log("bench: fusion forms at the headline size (fused, two-pass scan, unfused, LCG)")
+        result["fusion"] = bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, N_HEADLINE, x, y, ws)
+        if args.fusion_sweep:
+            sweep = []
+            for bits in range(20, 30):
+                for n in (1 << bits, (1 << bits) + 1):
+                    log(f"bench: fusion sweep n={n}")
+                    sweep.append(bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n))
+            result["fusion_sweep"] = sweep
 
     if not args.no_batched:
         log("bench: batched vs per-call (4,096 segments, log-uniform sizes in [100, 10^6], PCG64 seed 3)")

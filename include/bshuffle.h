@@ -145,10 +145,48 @@ bs_status bs_shuffle_batched(const void *in, void *out, const int64_t *offsets,
                              size_t workspace_bytes, void *stream);
 
 /*
+ * bs_permutation -- the permutation itself: out_idx[j] = the input position
+ * of the record that bs_shuffle(n, seed, rounds) puts at output j, i.e. f(i)
+ * for the j-th kept padded index (Algorithm 1 with the index as payload).
+ * index_bytes is 4 (n <= 2^32) or 8; out_idx is a device array of n indices
+ * aligned to index_bytes.  Workspace and stream as for bs_shuffle.
+ */
+bs_status bs_permutation(void *out_idx, uint64_t n, uint32_t index_bytes, uint64_t seed, uint32_t rounds,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * bs_unshuffle -- the inverse of bs_shuffle with the same (n, seed, rounds):
+ * out[f(i)] = in[rank(i)] for every kept padded index i (VariablePhilox is
+ * a bijection, Sec. 3.2; its inverse permutation undoes the shuffle), so
+ * bs_unshuffle(bs_shuffle(x)) == x.  Reads are coalesced, writes scattered.
+ * Arguments and errors as for bs_shuffle.
+ */
+bs_status bs_unshuffle(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t rounds,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * The linear congruential bijection of Sec. 3.1 as the shuffle's f, for
+ * comparison with VariablePhilox (Sec. 5 reports its poor quality: at n = 5
+ * its chi-square statistic is in the hundreds of thousands).
+ *
+ * bs_lcg_params -- the LCG of a call: f(x) = (a*x + c) mod 2^k with
+ * k = bs_domain_bits(n), a = (first SplitMix64 output of seed) | 1 and
+ * c = second output, both reduced mod 2^k.  Host only; BS_EINVAL for null
+ * pointers or n > BS_MAX_ITEMS.
+ *
+ * bs_shuffle_lcg -- Algorithm 1 with that f: out[rank(i)] = in[f(i)] over the
+ * kept padded indices i, in one fused pass as bs_shuffle.  Arguments, workspace
+ * and errors as for bs_shuffle (there are no rounds).
+ */
+bs_status bs_lcg_params(uint64_t n, uint64_t seed, uint64_t *a, uint64_t *c);
+bs_status bs_shuffle_lcg(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/*
  * Launch configuration (never changes results).  A tile is waves x 64 x items
  * padded indices; depth is how many tiles a workgroup keeps in flight.
  * Compiled shapes (waves, items, depth): (4,16,2) (8,16,2) (8,16,1)
- * (16,16,1) (16,8,1) (8,8,2) (4,16,1).  grid_mult: 0 = a persistent grid of
+ * (16,16,1) (16,8,1) (8,8,2) (4,16,1) (16,16,2) (16,8,2).  grid_mult: 0 = a persistent grid of
  * as many workgroups as the device keeps resident, 1..64 = that many
  * workgroups per CU, BS_GRID_ONE_PER_TILE = one workgroup per tile.
  * bs_set_config with a shape forces it for every later call (from every

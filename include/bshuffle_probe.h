@@ -33,6 +33,26 @@ bs_status bs_probe_gather(const void *in, uint64_t n_in, void *out, const uint32
 bs_status bs_probe_cipher_scan(uint64_t n, uint64_t seed, uint32_t rounds, void *workspace,
                                size_t workspace_bytes, void *stream);
 
+/*
+ * Less-fused forms of the same shuffle (Sec. 6's "Bijective1" and
+ * "Bijective0"), for measurement; both write exactly bs_shuffle's output.
+ *
+ * bs_probe_shuffle_two_pass: the kept count of every tile first (cipher, no
+ * payload), an exclusive scan of the counts, then the fused gather with known
+ * tile prefixes (the cipher runs twice, no look-back).  n <= 2^32.
+ *
+ * bs_probe_shuffle_unfused: f over the whole padded domain written to a
+ * table, a stream compaction of the images < n into a source list, then a
+ * random gather through that list.  scratch: device memory of at least
+ * bs_probe_unfused_scratch_bytes(n) bytes, 256-byte aligned.  n <= 2^32.
+ */
+bs_status bs_probe_shuffle_two_pass(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                    uint32_t rounds, void *workspace, size_t workspace_bytes, void *stream);
+size_t bs_probe_unfused_scratch_bytes(uint64_t n);
+bs_status bs_probe_shuffle_unfused(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                   uint32_t rounds, void *scratch, size_t scratch_bytes, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
 /* Selects plain (0) or non-temporal (1) output stores for bs_shuffle. */
 bs_status bs_probe_set_store_mode(uint32_t nontemporal);
 

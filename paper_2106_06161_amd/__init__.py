@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     BShuffleError,
     bs_domain_bits,
     bs_get_config,
+    bs_lcg_params,
     bs_round_keys,
     bs_set_config,
     bs_shuffle,
@@ -23,8 +24,11 @@ from .binding import (  # noqa: F401
     bs_workspace_error,
     bs_workspace_init,
     make_workspace,
+    permutation,
     shuffle,
     shuffle_batched,
+    shuffle_lcg,
+    unshuffle,
     workspace_bytes,
     workspace_error,
 )

@@ -50,6 +50,13 @@ _SIGNATURES = {
     "bs_set_tuned_config": (_i32, [_u32, _u32, _u32, _u32, _u32, _u32, _u32]),
     "bs_clear_tuned_configs": (_i32, []),
     "bs_query_config": (_i32, [_u32, _u32, _u64, _u32, _vp, _vp, _vp, _vp]),
+    "bs_permutation": (_i32, [_vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
+    "bs_unshuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
+    "bs_lcg_params": (_i32, [_u64, _u64, _vp, _vp]),
+    "bs_shuffle_lcg": (_i32, [_vp, _vp, _u64, _u32, _u64, _vp, _sz, _vp]),
+    "bs_probe_shuffle_two_pass": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
+    "bs_probe_unfused_scratch_bytes": (_sz, [_u64]),
+    "bs_probe_shuffle_unfused": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp, _sz, _vp]),
     "bs_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
@@ -162,6 +169,43 @@ def bs_clear_tuned_configs() -> int:
     return int(lib().bs_clear_tuned_configs())
 
 
+def bs_permutation(out_ptr, n, index_bytes, seed, rounds, workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_permutation(out_ptr, n, index_bytes, seed & (2**64 - 1), rounds, workspace,
+                                    workspace_bytes, stream))
+
+
+def bs_unshuffle(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_unshuffle(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, workspace,
+                                  workspace_bytes, stream))
+
+
+def bs_lcg_params(n: int, seed: int) -> tuple[int, int]:
+    a, c = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().bs_lcg_params(n, seed & (2**64 - 1), ctypes.byref(a), ctypes.byref(c)), "bs_lcg_params")
+    return a.value, c.value
+
+
+def bs_shuffle_lcg(in_ptr, out_ptr, n, elem_bytes, seed, workspace, workspace_bytes, stream) -> int:
+    return int(lib().bs_shuffle_lcg(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), workspace, workspace_bytes,
+                                    stream))
+
+
+def bs_probe_shuffle_two_pass(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, workspace_bytes,
+                              stream) -> int:
+    return int(lib().bs_probe_shuffle_two_pass(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds,
+                                               workspace, workspace_bytes, stream))
+
+
+def bs_probe_unfused_scratch_bytes(n: int) -> int:
+    return int(lib().bs_probe_unfused_scratch_bytes(n))
+
+
+def bs_probe_shuffle_unfused(in_ptr, out_ptr, n, elem_bytes, seed, rounds, scratch, scratch_bytes, workspace,
+                             workspace_bytes, stream) -> int:
+    return int(lib().bs_probe_shuffle_unfused(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, scratch,
+                                              scratch_bytes, workspace, workspace_bytes, stream))
+
+
 def bs_probe_copy(in_ptr, out_ptr, nbytes, stream) -> int:
     return int(lib().bs_probe_copy(in_ptr, out_ptr, nbytes, stream))
 
@@ -262,6 +306,57 @@ def shuffle_batched(x, offsets, seeds, rounds: int = DEFAULT_ROUNDS, out=None, t
         st = bs_shuffle_batched(x.data_ptr(), out.data_ptr(), offsets.data_ptr(), seeds.data_ptr(), s, total, eb,
                                 rounds, ws_ptr, ws_bytes, _stream_ptr(x, stream))
     _check(st, "bs_shuffle_batched")
+    return out
+
+
+def permutation(n: int, seed: int, rounds: int = DEFAULT_ROUNDS, index_dtype=None, device="cuda", out=None,
+                workspace=None, stream=None):
+    """The shuffle's gather map: out[j] = input position of output j (int32 or int64)."""
+    import torch
+
+    index_dtype = index_dtype or (torch.int32 if n <= (1 << 31) else torch.int64)
+    if out is None:
+        out = torch.empty(n, dtype=index_dtype, device=device)
+    _require_device(out, "out")
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
+    with torch.cuda.device(out.device):
+        st = bs_permutation(out.data_ptr(), n, out.element_size(), seed, rounds, ws_ptr, ws_bytes,
+                            _stream_ptr(out, stream))
+    _check(st, "bs_permutation")
+    return out
+
+
+def unshuffle(y, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, workspace=None, stream=None):
+    """Inverse of shuffle(x, seed, rounds) along dim 0."""
+    import torch
+
+    _require_device(y, "y")
+    if out is None:
+        out = torch.empty_like(y)
+    _require_device(out, "out")
+    n, eb = _records(y)
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
+    with torch.cuda.device(y.device):
+        st = bs_unshuffle(y.data_ptr(), out.data_ptr(), n, eb, seed, rounds, ws_ptr, ws_bytes, _stream_ptr(y, stream))
+    _check(st, "bs_unshuffle")
+    return out
+
+
+def shuffle_lcg(x, seed: int, out=None, workspace=None, stream=None):
+    """Shuffle of x along dim 0 with the LCG bijection (Sec. 3.1) in place of VariablePhilox."""
+    import torch
+
+    _require_device(x, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    _require_device(out, "out")
+    if out.shape != x.shape or out.dtype != x.dtype:
+        raise ValueError("out must match x in shape and dtype")
+    n, eb = _records(x)
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
+    with torch.cuda.device(x.device):
+        st = bs_shuffle_lcg(x.data_ptr(), out.data_ptr(), n, eb, seed, ws_ptr, ws_bytes, _stream_ptr(x, stream))
+    _check(st, "bs_shuffle_lcg")
     return out
 
 

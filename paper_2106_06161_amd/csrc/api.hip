@@ -154,6 +154,22 @@ bs_status resolve_workspace(void* user, size_t user_bytes, size_t need, hipStrea
   return BS_OK;
 }
 
+// Cipher parameters and masked round keys of one call (Sec. 3.2 split, keys
+// from SplitMix64 masked to the half width, then a 0).
+void setup_cipher(bsd::SingleArgs& a, uint64_t n, uint64_t seed, uint32_t rounds) {
+  const uint32_t k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
+  a.n = n;
+  a.domain = uint64_t(1) << k;
+  a.cs.w = k / 2;
+  a.cs.r = k - a.cs.w;
+  a.cs.wmask = (1u << a.cs.w) - 1u;
+  a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
+  a.rounds = rounds;
+  uint64_t st = seed;
+  for (uint32_t r = 0; r < rounds; ++r) a.key[r] = uint32_t(splitmix64_step(st)) & a.cs.wmask;
+  a.key[rounds] = 0;
+}
+
 bool ranges_overlap(const void* a, const void* b, uint64_t bytes) {
   const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
   return x < y + bytes && y < x + bytes;
@@ -428,4 +444,147 @@ extern "C" bs_status bs_probe_cipher_scan(uint64_t n, uint64_t seed, uint32_t ro
   if (st != BS_OK) return st;
   e = bsd::launch_single(a, 0, false, cfg, cus, s);
   return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+// ---------------------------------------------------- permutation outputs --
+namespace {
+
+// Runs one fixed-shape kernel variant over a single shuffle's domain.
+bs_status run_variant(bsd::SingleArgs& a, uint32_t variant, uint32_t eb, void* workspace, size_t workspace_bytes,
+                      hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  const bool wide = a.domain > (uint64_t(1) << 32);
+  const uint64_t tile = wide ? 64ull * bsd::kWideWaves * bsd::kWideItems : bsd::kAltTile;
+  a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
+  void* ws = nullptr;
+  bs_status st = resolve_workspace(workspace, workspace_bytes, bs_workspace_bytes(a.n, 0, eb), s, &ws);
+  if (st != BS_OK) return st;
+  a.hdr = static_cast<bsd::WorkspaceHeader*>(ws);
+  a.status = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(ws) + kHeaderBytes);
+  a.capacity = uint32_t(single_capacity(a.n));
+  a.nontemporal = g_nontemporal_store ? 1u : 0u;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t cus = 0;
+  st = device_cus(dev, &cus);
+  if (st != BS_OK) return st;
+  if (variant == bsd::kVarTwoPass) {
+    // counts and exclusive prefixes live in the status array (64-bit values
+    // with a zero tag, i.e. "nothing yet" to any later look-back)
+    a.tile_counts = a.status;
+    a.tile_prefix = a.status + a.num_tiles;
+    e = bsd::launch_tile_counts(a, s);
+    if (e == hipSuccess) e = bsd::launch_tile_prefix(a.tile_counts, a.status + a.num_tiles, a.num_tiles, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  e = bsd::launch_variant(a, variant, eb, cus, s);
+  return e == hipSuccess ? BS_OK : (e == hipErrorInvalidValue ? BS_EINVAL : hip_fail(e));
+}
+
+}  // namespace
+
+extern "C" bs_status bs_permutation(void* out_idx, uint64_t n, uint32_t index_bytes, uint64_t seed,
+                                    uint32_t rounds, void* workspace, size_t workspace_bytes, void* stream) {
+  if (index_bytes != 4 && index_bytes != 8) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!out_idx) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(out_idx) % index_bytes) return BS_EELEM;
+  if (index_bytes == 4 && n > (uint64_t(1) << 32)) return BS_EINVAL;
+  bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, rounds);
+  a.out = static_cast<uint8_t*>(out_idx);
+  return run_variant(a, bsd::kVarIndices, index_bytes, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" bs_status bs_unshuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                  uint32_t rounds, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
+  bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, rounds);
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  return run_variant(a, bsd::kVarScatter, elem_bytes, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" bs_status bs_probe_shuffle_two_pass(const void* in, void* out, uint64_t n, uint32_t elem_bytes,
+                                               uint64_t seed, uint32_t rounds, void* workspace,
+                                               size_t workspace_bytes, void* stream) {
+  if (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8 && elem_bytes != 16) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > (uint64_t(1) << 32)) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
+  bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, rounds);
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  return run_variant(a, bsd::kVarTwoPass, elem_bytes, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t bs_probe_unfused_scratch_bytes(uint64_t n) {
+  const uint64_t domain = uint64_t(1) << bs_domain_bits(n);
+  return align256(domain * 4) + align256(n * 4);
+}
+
+extern "C" bs_status bs_probe_shuffle_unfused(const void* in, void* out, uint64_t n, uint32_t elem_bytes,
+                                              uint64_t seed, uint32_t rounds, void* scratch, size_t scratch_bytes,
+                                              void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > (uint64_t(1) << 32)) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out || !scratch) return BS_EINVAL;
+  if (scratch_bytes < bs_probe_unfused_scratch_bytes(n)) return BS_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(scratch) % 256) return BS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, rounds);
+  uint32_t* table = static_cast<uint32_t*>(scratch);
+  uint32_t* sources = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(scratch) + align256(a.domain * 4));
+  // pass 1: f over the whole padded domain
+  hipError_t e = bsd::launch_cipher_table(a, table, s);
+  if (e != hipSuccess) return hip_fail(e);
+  // pass 2: stream compaction of the images < n into the source list
+  a.table = table;
+  a.out = reinterpret_cast<uint8_t*>(sources);
+  bs_status st = run_variant(a, bsd::kVarFromTable, 4, workspace, workspace_bytes, s);
+  if (st != BS_OK) return st;
+  // pass 3: the gather
+  return bs_probe_gather(in, n, out, sources, n, elem_bytes, stream);
+}
+
+// ------------------------------------------------------------ LCG variant --
+extern "C" bs_status bs_lcg_params(uint64_t n, uint64_t seed, uint64_t* a, uint64_t* c) {
+  if (!a || !c || n > BS_MAX_ITEMS) return BS_EINVAL;
+  const uint64_t mask = (uint64_t(1) << bs_domain_bits(n)) - 1;
+  uint64_t st = seed;
+  *a = (splitmix64_step(st) | 1u) & mask;
+  *c = splitmix64_step(st) & mask;
+  return BS_OK;
+}
+
+extern "C" bs_status bs_shuffle_lcg(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
+  bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, 0);
+  bs_lcg_params(n, seed, &a.lcg_a, &a.lcg_c);
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  return run_variant(a, bsd::kVarLcg, elem_bytes, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }

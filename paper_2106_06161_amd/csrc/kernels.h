@@ -24,6 +24,10 @@ struct SingleArgs {
   uint32_t nontemporal;  // 1: output stores bypass cache retention
   WorkspaceHeader* hdr;
   uint64_t* status;
+  const uint32_t* table;        // unfused variant: f over the padded domain
+  const uint64_t* tile_prefix;  // two-pass variant: exclusive prefix of every tile
+  uint64_t* tile_counts;        // two-pass variant: kept count of every tile
+  uint64_t lcg_a, lcg_c;        // LCG variant: multiplier (odd) and increment, both < 2^k
   uint32_t key[kMaxRounds + 1];  // round keys masked to the half width, then 0
 };
 
@@ -67,6 +71,11 @@ hipError_t launch_single(const SingleArgs& a, uint32_t elem_bytes, bool nontempo
 hipError_t launch_batched(const BatchArgs& a, uint32_t elem_bytes, const LaunchConfig& cfg, uint32_t num_cus,
                           hipStream_t stream);
 hipError_t launch_workspace_init(void* ws, size_t bytes, hipStream_t stream);
+hipError_t launch_variant(const SingleArgs& a, uint32_t variant, uint32_t elem_bytes, uint32_t num_cus,
+                          hipStream_t stream);
+hipError_t launch_tile_counts(const SingleArgs& a, hipStream_t stream);
+hipError_t launch_tile_prefix(const uint64_t* counts, uint64_t* prefix, uint32_t tiles, hipStream_t stream);
+hipError_t launch_cipher_table(const SingleArgs& a, uint32_t* table, hipStream_t stream);
 
 bool config_supported(const LaunchConfig& cfg);
 
@@ -80,9 +89,21 @@ using BatchFn = void (*)(BatchArgs);
 // Shape used when the index space needs 64 bits (k > 32).
 constexpr uint32_t kWideWaves = 8, kWideItems = 16;
 
+// Kernel variants (fixed tile shape 16 waves x 16 items): what a kept index
+// produces (0 gather, 1 index, 2 scatter), and how the tile prefix is found.
+enum Variant : uint32_t {
+  kVarIndices = 1,   // out[rank] = f(i)               (bs_permutation)
+  kVarScatter = 2,   // out[f(i)] = in[rank]           (bs_unshuffle)
+  kVarTwoPass = 3,   // gather, tile prefixes from a separate scan pass
+  kVarFromTable = 4,  // compaction of a precomputed f table into indices
+  kVarLcg = 5         // gather with the LCG as the bijection      (bs_shuffle_lcg)
+};
+constexpr uint32_t kAltTile = 16u * 64u * 16u;
+
 #define BSD_DECLARE_PICK(EB)                                                    \
   SingleFn pick_single_##EB(bool odd, bool wide, const LaunchConfig& c);        \
-  BatchFn pick_batch_##EB(const LaunchConfig& c);
+  BatchFn pick_batch_##EB(const LaunchConfig& c);                               \
+  SingleFn pick_variant_##EB(uint32_t variant, bool odd, bool wide);
 BSD_DECLARE_PICK(0)
 BSD_DECLARE_PICK(1)
 BSD_DECLARE_PICK(2)

@@ -123,20 +123,40 @@ __device__ __forceinline__ void group_end(WorkspaceHeader* hdr, uint64_t* status
 //   gather: cipher, keep flags, wave-local ranks, random loads issued;
 //   scan:   workgroup scan of the wave counts and the decoupled look-back;
 //   store:  kept records written at prefix + rank.
-constexpr uint32_t kDropped = 0xFFFFFFFFu;
+//
+// MODE selects what a kept padded index i (image y = f(i), output rank r)
+// produces:
+//   kGather   out[r] = in[y]              the shuffle (Algorithm 1)
+//   kIndices  out[r] = y                  the permutation itself (gather map)
+//   kScatter  out[y] = in[r]              the inverse shuffle
+//   kCount    nothing; tile totals only   first pass of the two-pass variant
+// BIJ selects the bijection f:
+//   kBijPhilox  VariablePhilox (Sec. 3.2), the shuffle's bijection
+//   kBijTable   y read from a precomputed table of f over the padded domain
+//               (the unfused variant's compaction pass)
+//   kBijLcg     y = (a*i + c) mod 2^k, a odd (the LCG of Sec. 3.1)
+enum Mode : int { kGather = 0, kIndices = 1, kScatter = 2, kCount = 3 };
+enum Bijection : int { kBijPhilox = 0, kBijTable = 1, kBijLcg = 2 };
 
-template <int EB, int ITEMS>
-struct PendingTile {
-  typename Payload<EB>::T val[ITEMS];  // gathered records (loads may be in flight)
-  uint32_t keep_bits;                  // bit j: this lane keeps its index of item j
-  uint32_t wave_count;                 // kept indices of this wave (uniform)
+template <int EB, int MODE, bool WIDE>
+struct ItemValue {
+  using Idx = std::conditional_t<WIDE, uint64_t, uint32_t>;
+  using T = std::conditional_t<MODE == kGather, typename Payload<EB>::T, Idx>;
 };
-static_assert(kDropped != 0, "");
 
-template <int EB, bool ODD, int WAVES, int ITEMS, bool WIDE>
-__device__ __forceinline__ void tile_gather(PendingTile<EB, ITEMS>& t, const uint8_t* __restrict__ in, uint64_t n,
-                                            uint64_t domain, const CipherShape cs, uint32_t rounds,
-                                            const uint32_t* __restrict__ keys, uint64_t tile_in_segment) {
+template <int EB, int MODE, int ITEMS, bool WIDE>
+struct PendingTile {
+  typename ItemValue<EB, MODE, WIDE>::T val[ITEMS];  // gathered record, or the image y
+  uint32_t keep_bits;                                // bit j: this lane keeps item j's index
+  uint32_t wave_count;                               // kept indices of this wave (uniform)
+};
+
+template <int EB, int MODE, bool ODD, int WAVES, int ITEMS, bool WIDE, int BIJ = kBijPhilox>
+__device__ __forceinline__ void tile_gather(PendingTile<EB, MODE, ITEMS, WIDE>& t, const uint8_t* __restrict__ in,
+                                            uint64_t n, uint64_t domain, const CipherShape cs, uint32_t rounds,
+                                            const uint32_t* __restrict__ keys, uint64_t tile_in_segment,
+                                            const uint32_t* __restrict__ table = nullptr, uint64_t lcg_a = 0,
+                                            uint64_t lcg_c = 0) {
   using Idx = std::conditional_t<WIDE, uint64_t, uint32_t>;
   constexpr uint32_t kTile = 64u * WAVES * ITEMS;
   const uint32_t lane = threadIdx.x & 63u;
@@ -162,21 +182,36 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, ITEMS>& t, const uin
     Idx x = base + Idx(s0 * 64);
 #pragma unroll
     for (int j = 0; j < kSub; ++j, x += 64) {
-      L[j] = uint32_t(x >> cs.r) & wmask24;
-      R[j] = uint32_t(x);
-      if (!whole_tile) in_domain |= (x <= x_last) ? (1u << j) : 0u;
+      const bool inside = whole_tile || x <= x_last;
+      if (!whole_tile) in_domain |= inside ? (1u << j) : 0u;
+      if constexpr (BIJ == kBijTable) {
+        L[j] = inside ? table[x] : 0u;  // the image itself (narrow domains only)
+      } else if constexpr (BIJ == kBijPhilox) {
+        L[j] = uint32_t(x >> cs.r) & wmask24;
+        R[j] = uint32_t(x);
+      }
     }
-    vp_encrypt<ODD, kSub>(L, R, cs, rounds, keys);
+    if constexpr (BIJ == kBijPhilox) vp_encrypt<ODD, kSub>(L, R, cs, rounds, keys);
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const Idx y = (Idx(L[j]) << cs.r) | Idx(R[j] & cs.rmask);
+      Idx y;
+      if constexpr (BIJ == kBijTable) {
+        y = Idx(L[j]);
+      } else if constexpr (BIJ == kBijLcg) {
+        // arithmetic mod 2^32 (narrow) or 2^64 (wide), then mod 2^k
+        y = (Idx(lcg_a) * (base + Idx((s0 + j) * 64)) + Idx(lcg_c)) & x_last;
+      } else {
+        y = (Idx(L[j]) << cs.r) | Idx(R[j] & cs.rmask);
+      }
       // keep: the padded index is inside the domain and its image is < n
       // (as "<= last" so the narrow path compares in 32 bits: n, 2^k <= 2^32)
       const bool keep = ((in_domain >> j) & 1u) && (y <= y_last);
       const uint64_t m = __ballot(keep);
       keep_bits |= keep ? (1u << (s0 + j)) : 0u;
-      if constexpr (EB > 0) {
+      if constexpr (MODE == kGather && EB > 0) {
         if (keep) t.val[s0 + j] = load_record<EB>(in, uint64_t(y));
+      } else if constexpr (MODE == kIndices || MODE == kScatter) {
+        t.val[s0 + j] = y;
       }
       wave_count += uint32_t(__builtin_popcountll(m));
     }
@@ -185,12 +220,14 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, ITEMS>& t, const uin
   t.keep_bits = keep_bits;
 }
 
-// Returns this wave's output base: kept indices before the tile (look-back)
-// plus those of lower waves in the tile.  Takes the workgroup's next ticket.
-template <int WAVES>
+// Returns this wave's output base: kept indices before the tile plus those
+// of lower waves in the tile.  With LOOKBACK the tile's prefix comes from the
+// decoupled look-back; otherwise from tile_prefix[status_idx] (written by an
+// earlier pass).  Takes the workgroup's next ticket.
+template <int WAVES, bool LOOKBACK = true>
 __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* status, uint32_t status_first,
                                               uint32_t status_idx, uint32_t tag, WorkspaceHeader* hdr,
-                                              TileLds<WAVES>& lds) {
+                                              TileLds<WAVES>& lds, const uint64_t* tile_prefix = nullptr) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (lane == 0) lds.wave_count[wave] = wave_count;
@@ -205,23 +242,30 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
   constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
   if (wave == kTicketWave && lane == 0) lds.next_ticket = atomicAdd(&hdr->ticket, 1u);
   if (wave == 0) {
-    const uint64_t ex =
-        lookback_exclusive_prefix(status, status_first, status_idx, tag, uint64_t(tile_total), &hdr->error);
+    uint64_t ex;
+    if constexpr (LOOKBACK)
+      ex = lookback_exclusive_prefix(status, status_first, status_idx, tag, uint64_t(tile_total), &hdr->error);
+    else
+      ex = tile_prefix[status_idx];
     if (lane == 0) lds.tile_exclusive = ex;
   }
   __syncthreads();
   return lds.tile_exclusive + wave_exclusive;
 }
 
-// Writes the kept records: item j's kept lanes go to consecutive positions
+// Writes the kept items: item j's kept lanes take consecutive ranks
 // prefix + (kept before item j in this wave) + (kept lanes below this lane),
-// the ballot and rank being recomputed here from the keep bits.  Positions
-// are < n by construction; the bound check only keeps a timed-out look-back
-// from writing outside the buffer.
-template <int EB, int ITEMS>
-__device__ __forceinline__ void tile_store(const PendingTile<EB, ITEMS>& t, uint8_t* __restrict__ out, uint64_t n,
-                                           uint64_t prefix, bool nontemporal) {
-  if constexpr (EB > 0) {
+// the ballot and rank being recomputed here from the keep bits.  Ranks are
+// < n by construction; the bound check only keeps a timed-out look-back from
+// writing outside the buffer.  EB is the record size (kGather, kScatter) or
+// the index size (kIndices: 4 or 8).
+template <int EB, int MODE, int ITEMS, bool WIDE>
+__device__ __forceinline__ void tile_store(const PendingTile<EB, MODE, ITEMS, WIDE>& t, const uint8_t* __restrict__ in,
+                                           uint8_t* __restrict__ out, uint64_t n, uint64_t prefix,
+                                           bool nontemporal) {
+  if constexpr (MODE == kCount || EB == 0) {
+    return;
+  } else {
     uint64_t base = prefix;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -231,10 +275,17 @@ __device__ __forceinline__ void tile_store(const PendingTile<EB, ITEMS>& t, uint
           __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
       const uint64_t pos = base + below;
       if (keep && pos < n) {
-        if (nontemporal)
-          store_record<EB, true>(out, pos, t.val[j]);
-        else
-          store_record<EB, false>(out, pos, t.val[j]);
+        if constexpr (MODE == kGather) {
+          if (nontemporal)
+            store_record<EB, true>(out, pos, t.val[j]);
+          else
+            store_record<EB, false>(out, pos, t.val[j]);
+        } else if constexpr (MODE == kIndices) {
+          using IT = std::conditional_t<EB == 8, uint64_t, uint32_t>;
+          reinterpret_cast<IT*>(out)[pos] = IT(t.val[j]);
+        } else {  // kScatter: the record at rank pos goes back to position y
+          store_record<EB, false>(out, uint64_t(t.val[j]), load_record<EB>(in, pos));
+        }
       }
       base += uint64_t(__builtin_popcountll(m));
     }
@@ -247,12 +298,12 @@ __device__ __forceinline__ void tile_store(const PendingTile<EB, ITEMS>& t, uint
 // of the current tile are outstanding, then the current tile is stored.
 // DEPTH 1 finishes each tile before starting the next (fewer registers).
 // Minimum waves per SIMD the register budget is sized for (HIP's second
-// launch-bounds argument).  Two 16-wave groups per CU (8 waves per SIMD, at
-// most 64 VGPRs) keep one group's gathers in flight while the other computes.
+// launch-bounds argument).
 template <int WAVES, int DEPTH>
 constexpr int kMinWavesPerSimd = 1;
 
-template <int EB, bool ODD, int WAVES, int ITEMS, int DEPTH, bool WIDE>
+template <int EB, bool ODD, int WAVES, int ITEMS, int DEPTH, bool WIDE, int MODE = kGather, bool LOOKBACK = true,
+          int BIJ = kBijPhilox>
 __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void shuffle_single_kernel(
     const SingleArgs a) {
   __shared__ TileLds<WAVES> lds;
@@ -262,33 +313,59 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void 
   const bool nt = a.nontemporal != 0;
   uint32_t tile = lds.ticket;
   if constexpr (DEPTH == 1) {
-    PendingTile<EB, ITEMS> cur;
+    PendingTile<EB, MODE, ITEMS, WIDE> cur;
     while (tile < a.num_tiles) {
-      tile_gather<EB, ODD, WAVES, ITEMS, WIDE>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile);
-      const uint64_t prefix = tile_scan(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds);
-      tile_store(cur, a.out, a.n, prefix, nt);
+      tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile,
+                                                          a.table, a.lcg_a, a.lcg_c);
+      const uint64_t prefix =
+          tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.tile_prefix);
+      tile_store(cur, a.in, a.out, a.n, prefix, nt);
       tile = lds.next_ticket;
     }
   } else {
-    PendingTile<EB, ITEMS> cur, nxt;
+    PendingTile<EB, MODE, ITEMS, WIDE> cur, nxt;
     uint64_t cur_prefix = 0;
     if (tile < a.num_tiles) {
-      tile_gather<EB, ODD, WAVES, ITEMS, WIDE>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile);
-      cur_prefix = tile_scan(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds);
+      tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile,
+                                                          a.table, a.lcg_a, a.lcg_c);
+      cur_prefix = tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.tile_prefix);
     }
     while (tile < a.num_tiles) {
       const uint32_t next = lds.next_ticket;
       const bool more = next < a.num_tiles;
-      if (more) tile_gather<EB, ODD, WAVES, ITEMS, WIDE>(nxt, a.in, a.n, a.domain, a.cs, a.rounds, a.key, next);
-      tile_store(cur, a.out, a.n, cur_prefix, nt);
+      if (more)
+        tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(nxt, a.in, a.n, a.domain, a.cs, a.rounds, a.key, next,
+                                                            a.table, a.lcg_a, a.lcg_c);
+      tile_store(cur, a.in, a.out, a.n, cur_prefix, nt);
       if (more) {
-        cur_prefix = tile_scan(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds);
+        cur_prefix = tile_scan<WAVES, LOOKBACK>(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds, a.tile_prefix);
         cur = nxt;
       }
       tile = next;
     }
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds);
+}
+
+// First pass of the two-pass scan variant: the kept count of every tile,
+// written to tile_counts[tile] (no look-back, no payload).  One workgroup per
+// tile, in any order.
+template <bool ODD, int WAVES, int ITEMS>
+__global__ __launch_bounds__(WAVES * 64) void tile_count_kernel(const SingleArgs a) {
+  __shared__ uint32_t wave_counts[WAVES];
+  for (uint32_t tile = blockIdx.x; tile < a.num_tiles; tile += gridDim.x) {
+    PendingTile<0, kCount, ITEMS, false> t;
+    tile_gather<0, kCount, ODD, WAVES, ITEMS, false>(t, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile);
+    const uint32_t wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63u) == 0) wave_counts[wave] = t.wave_count;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t total = 0;
+      for (int w = 0; w < WAVES; ++w) total += wave_counts[w];
+      a.tile_counts[tile] = total;
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------- batched kernels --
@@ -340,11 +417,14 @@ __device__ __forceinline__ BatchTile batch_tile(const BatchArgs& a, uint32_t til
 }
 
 template <int EB, int WAVES, int ITEMS>
-__device__ __forceinline__ void batch_gather(PendingTile<EB, ITEMS>& t, const BatchTile& b, uint32_t rounds) {
+__device__ __forceinline__ void batch_gather(PendingTile<EB, kGather, ITEMS, false>& t, const BatchTile& b,
+                                             uint32_t rounds) {
   if (b.odd)
-    tile_gather<EB, true, WAVES, ITEMS, false>(t, b.in, b.n, b.domain, b.cs, rounds, b.keys, b.tile_in_segment);
+    tile_gather<EB, kGather, true, WAVES, ITEMS, false>(t, b.in, b.n, b.domain, b.cs, rounds, b.keys,
+                                                        b.tile_in_segment);
   else
-    tile_gather<EB, false, WAVES, ITEMS, false>(t, b.in, b.n, b.domain, b.cs, rounds, b.keys, b.tile_in_segment);
+    tile_gather<EB, kGather, false, WAVES, ITEMS, false>(t, b.in, b.n, b.domain, b.cs, rounds, b.keys,
+                                                         b.tile_in_segment);
 }
 
 template <int EB, int WAVES, int ITEMS, int DEPTH>
@@ -358,16 +438,16 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void 
   const bool nt = a.nontemporal != 0;
   uint32_t tile = lds.ticket;
   if constexpr (DEPTH == 1) {
-    PendingTile<EB, ITEMS> cur;
+    PendingTile<EB, kGather, ITEMS, false> cur;
     while (tile < limit) {
       const BatchTile b = batch_tile<EB>(a, tile);
       batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
       const uint64_t prefix = tile_scan(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
-      tile_store(cur, b.out, b.n, prefix, nt);
+      tile_store(cur, nullptr, b.out, b.n, prefix, nt);
       tile = lds.next_ticket;
     }
   } else {
-    PendingTile<EB, ITEMS> cur, nxt;
+    PendingTile<EB, kGather, ITEMS, false> cur, nxt;
     uint64_t cur_prefix = 0;
     uint8_t* cur_out = nullptr;
     uint64_t cur_n = 0;
@@ -386,7 +466,7 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void 
         b = batch_tile<EB>(a, next);
         batch_gather<EB, WAVES, ITEMS>(nxt, b, a.rounds);
       }
-      tile_store(cur, cur_out, cur_n, cur_prefix, nt);
+      tile_store(cur, nullptr, cur_out, cur_n, cur_prefix, nt);
       if (more) {
         cur_prefix = tile_scan(nxt.wave_count, a.status, b.first_tile, next, tag, a.hdr, lds);
         cur = nxt;
@@ -397,6 +477,30 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void 
     }
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds);
+}
+
+// Variants outside the main shape table use one fixed shape.
+constexpr int kAltWaves = 16, kAltItems = 16;
+
+template <int EB, int MODE, bool LOOKBACK, int BIJ>
+SingleFn pick_variant_eb(bool odd, bool wide) {
+  if constexpr (BIJ == kBijTable) {  // the table holds 32-bit images: narrow domains only
+    if (wide) return nullptr;
+    return odd ? &shuffle_single_kernel<EB, true, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>
+               : &shuffle_single_kernel<EB, false, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>;
+  } else if constexpr (BIJ == kBijLcg) {  // no Feistel halves: odd and even k share a kernel
+    if (wide) return &shuffle_single_kernel<EB, false, kWideWaves, kWideItems, 1, true, MODE, LOOKBACK, BIJ>;
+    return &shuffle_single_kernel<EB, false, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>;
+  } else {
+    if (wide) {
+      if constexpr (!LOOKBACK) return nullptr;
+      if constexpr (MODE == kIndices && EB == 4) return nullptr;  // 64-bit images need 8-byte indices
+      return odd ? &shuffle_single_kernel<EB, true, kWideWaves, kWideItems, 1, true, MODE, LOOKBACK, BIJ>
+                 : &shuffle_single_kernel<EB, false, kWideWaves, kWideItems, 1, true, MODE, LOOKBACK, BIJ>;
+    }
+    return odd ? &shuffle_single_kernel<EB, true, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>
+               : &shuffle_single_kernel<EB, false, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>;
+  }
 }
 
 // ------------------------------------------------------------ dispatch --

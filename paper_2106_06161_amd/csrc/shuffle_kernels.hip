@@ -188,12 +188,110 @@ hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& c
   return hipGetLastError();
 }
 
+// Exclusive scan of per-tile counts (one workgroup; the tile count is small).
+__global__ __launch_bounds__(1024) void tile_prefix_kernel(const uint64_t* counts, uint64_t* prefix, uint32_t tiles) {
+  __shared__ uint64_t warp_sums[16];
+  __shared__ uint64_t carry;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, warp = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < tiles; base += 1024) {
+    const uint32_t i = base + tid;
+    const uint64_t c = i < tiles ? counts[i] : 0;
+    uint64_t v = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t t = __shfl_up(v, off, 64);
+      if (lane >= uint32_t(off)) v += t;
+    }
+    if (lane == 63) warp_sums[warp] = v;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      before += (w < warp) ? warp_sums[w] : 0;
+      total += warp_sums[w];
+    }
+    if (i < tiles) prefix[i] = carry + before + v - c;
+    __syncthreads();
+    if (tid == 0) carry += total;
+    __syncthreads();
+  }
+}
+
+// f(i) for every i of the padded domain (the unfused variant's first pass).
+template <bool ODD>
+__global__ __launch_bounds__(256) void cipher_table_kernel(const SingleArgs a, uint32_t* table) {
+  constexpr int kItems = 8;
+  const uint64_t stride = uint64_t(gridDim.x) * 256 * kItems;
+  for (uint64_t base = uint64_t(blockIdx.x) * 256 * kItems + threadIdx.x; base < a.domain; base += stride) {
+    uint32_t L[kItems], R[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t x = uint32_t(base + uint64_t(j) * 256);
+      L[j] = (x >> a.cs.r) & (a.cs.wmask & 0xFFFFFFu);
+      R[j] = x;
+    }
+    vp_encrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint64_t x = base + uint64_t(j) * 256;
+      if (x < a.domain) table[x] = (L[j] << a.cs.r) | (R[j] & a.cs.rmask);
+    }
+  }
+}
+
 hipError_t launch_workspace_init(void* ws, size_t bytes, hipStream_t stream) {
   const uint64_t words = bytes / 4;
   const uint64_t cap = bytes > sizeof(WorkspaceHeader) ? (bytes - sizeof(WorkspaceHeader)) / 8 : 0;
   const uint32_t blocks = uint32_t(std::min<uint64_t>(1024, (words + 255) / 256 + 1));
   hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(ws), words,
                      uint32_t(std::min<uint64_t>(cap, 0xFFFFFFFFull)));
+  return hipGetLastError();
+}
+
+hipError_t launch_variant(const SingleArgs& a, uint32_t variant, uint32_t eb, uint32_t num_cus, hipStream_t stream) {
+  const bool wide = a.domain > (uint64_t(1) << 32);
+  const bool odd = ((a.cs.w + a.cs.r) & 1u) != 0;
+  SingleFn fn = nullptr;
+  switch (eb) {
+    case 1: fn = pick_variant_1(variant, odd, wide); break;
+    case 2: fn = pick_variant_2(variant, odd, wide); break;
+    case 4: fn = pick_variant_4(variant, odd, wide); break;
+    case 8: fn = pick_variant_8(variant, odd, wide); break;
+    case 16: fn = pick_variant_16(variant, odd, wide); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (!fn) return hipErrorInvalidValue;
+  LaunchConfig cfg = {wide ? kWideWaves : uint32_t(kAltWaves), wide ? kWideItems : uint32_t(kAltItems), 1, 0};
+  const uint32_t grid = grid_for(a.num_tiles, cfg, num_cus, reinterpret_cast<const void*>(fn));
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * 64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_counts(const SingleArgs& a, hipStream_t stream) {
+  const bool odd = ((a.cs.w + a.cs.r) & 1u) != 0;
+  const uint32_t grid = std::max(1u, std::min(a.num_tiles, 4096u));
+  if (odd)
+    hipLaunchKernelGGL((tile_count_kernel<true, kAltWaves, kAltItems>), dim3(grid), dim3(kAltWaves * 64), 0, stream, a);
+  else
+    hipLaunchKernelGGL((tile_count_kernel<false, kAltWaves, kAltItems>), dim3(grid), dim3(kAltWaves * 64), 0, stream,
+                       a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_prefix(const uint64_t* counts, uint64_t* prefix, uint32_t tiles, hipStream_t stream) {
+  hipLaunchKernelGGL(tile_prefix_kernel, dim3(1), dim3(1024), 0, stream, counts, prefix, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_cipher_table(const SingleArgs& a, uint32_t* table, hipStream_t stream) {
+  const bool odd = ((a.cs.w + a.cs.r) & 1u) != 0;
+  const uint64_t want = (a.domain + 256 * 8 - 1) / (256 * 8);
+  const uint32_t grid = uint32_t(std::min<uint64_t>(want, 65536));
+  if (odd)
+    hipLaunchKernelGGL(cipher_table_kernel<true>, dim3(grid), dim3(256), 0, stream, a, table);
+  else
+    hipLaunchKernelGGL(cipher_table_kernel<false>, dim3(grid), dim3(256), 0, stream, a, table);
   return hipGetLastError();
 }
 

@@ -127,3 +127,31 @@ def test_shipped_tuned_table_is_valid():
     for e in entries:
         assert (e["waves"], e["items"], e["depth"]) in [tuple(s) for s in autotune.SHAPES]
     assert autotune.apply(entries) == len(entries)
+
+
+def test_permutation_and_unshuffle_argument_checks():
+    assert B.bs_permutation(FAKE_OUT, 10, 2, 1, 24, None, 0, None) == B.BS_EELEM
+    assert B.bs_permutation(FAKE_OUT + 2, 10, 4, 1, 24, None, 0, None) == B.BS_EELEM
+    assert B.bs_permutation(FAKE_OUT, (1 << 32) + 1, 4, 1, 24, None, 0, None) == B.BS_EINVAL
+    assert B.bs_permutation(None, 10, 4, 1, 24, None, 0, None) == B.BS_EINVAL
+    assert B.bs_permutation(None, 0, 4, 1, 24, None, 0, None) == B.BS_OK
+    assert B.bs_unshuffle(FAKE_IN, FAKE_IN, 10, 4, 1, 24, None, 0, None) == B.BS_EALIAS
+    assert B.bs_unshuffle(FAKE_IN, FAKE_OUT, 10, 3, 1, 24, None, 0, None) == B.BS_EELEM
+    assert B.bs_unshuffle(FAKE_IN, FAKE_OUT, 10, 4, 1, 65, None, 0, None) == B.BS_EINVAL
+    assert B.bs_probe_shuffle_two_pass(FAKE_IN, FAKE_OUT, (1 << 32) + 1, 4, 1, 24, None, 0, None) == B.BS_EINVAL
+    assert B.bs_probe_shuffle_unfused(FAKE_IN, FAKE_OUT, 100, 4, 1, 24, 1 << 42, 16, None, 0, None) == B.BS_ENOMEM
+    assert B.bs_probe_unfused_scratch_bytes(100_000) >= 4 * (1 << 17) + 4 * 100_000
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 1000, 65_537, 1 << 30, (1 << 32) + 1])
+def test_lcg_params_match_oracle(n):
+    for seed in (0, 1, 2**63 + 5):
+        assert B.bs_lcg_params(n, seed) == oracle.lcg_params(n, seed)
+
+
+def test_lcg_argument_checks():
+    assert B.bs_shuffle_lcg(FAKE_IN, FAKE_IN, 10, 4, 1, None, 0, None) == B.BS_EALIAS
+    assert B.bs_shuffle_lcg(FAKE_IN, FAKE_OUT, 10, 3, 1, None, 0, None) == B.BS_EELEM
+    assert B.bs_shuffle_lcg(None, FAKE_OUT, 10, 4, 1, None, 0, None) == B.BS_EINVAL
+    assert B.bs_shuffle_lcg(None, None, 0, 4, 1, None, 0, None) == B.BS_OK
+    assert B.bs_shuffle_lcg(FAKE_IN, FAKE_OUT, B.MAX_ITEMS + 1, 1, 1, None, 0, None) == B.BS_EINVAL

@@ -39,3 +39,16 @@ def test_mmd_pass_at_24_fail_at_4(n):
     assert abs(m24) < stats.normal_threshold(n, P, 0.01)
     m4 = stats.mmd2(gpu_permutations(n, 4))
     assert abs(m4) > stats.normal_threshold(n, P, 0.05)
+
+
+def test_lcg_chi_square_n5_is_huge():
+    """Sec. 5: the LCG bijection fails the n = 5 chi-square test by a wide
+    margin (hundreds of thousands against a critical value near 145)."""
+    x = torch.arange(5, dtype=torch.int32, device="cuda:0")
+    seeds = range(1, 20_001)
+    perms = np.stack([bs.shuffle_lcg(x, s).cpu().numpy() for s in seeds]).astype(np.uint32)
+    assert np.array_equal(perms, oracle.lcg_permutations(5, seeds))
+    chi, dof = stats.chi_square(perms)
+    # the statistic grows with the sample: ~5.6e5 at 100,000 permutations,
+    # ~1.1e5 at these 20,000
+    assert chi > 500 * stats.chi_square_critical(dof, 0.05)
