@@ -62,6 +62,13 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_label(launch: dict) -> str:
+    """The fused kernel that runs the headline step (even k, 32-bit indices)."""
+    if launch["depth"] == 8:  # kept images compacted through LDS
+        return "bsd::shuffle_compact_kernel<4, false, {waves}, {items}, 0>".format(**launch)
+    return "bsd::shuffle_single_kernel<4, false, {waves}, {items}, {depth}, false>".format(**launch)
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -380,7 +387,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
-            "kernel": "bsd::shuffle_single_kernel<4, even k, {waves}, {items}, {depth}, narrow>".format(**launch),
+            "kernel": kernel_label(launch),
             "kernel_ms": kernel_s * 1e3,
             "algorithmic_bytes_per_launch": alg_bytes,
             "kernel_source_digest": digest,

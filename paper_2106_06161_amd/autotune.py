@@ -2,8 +2,9 @@
 
 For each call kind (single bs_shuffle, batched bs_shuffle_batched), element
 size and size class it times every compiled tile shape (waves per workgroup,
-indices per lane, tiles in flight) with each grid choice, on seeded random
-data, and keeps the fastest.  The table is stored as JSON next to this file
+indices per lane, tile schedule: one or two tiles in flight with records in
+registers, or kept images compacted through LDS) with each grid choice, on
+seeded random data, and keeps the fastest.  The table is stored as JSON next to this file
 and handed to the library with bs_set_tuned_config when the library is
 loaded.  Launch shapes never change results, only speed.
 
@@ -20,6 +21,9 @@ from . import binding as B
 
 TUNED_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_configs.json")
 SHAPES = [(4, 16, 2), (8, 16, 2), (8, 16, 1), (16, 16, 1), (16, 8, 1), (8, 8, 2), (4, 16, 1), (16, 16, 2), (16, 8, 2)]
+# LDS-compacted schedule (single shuffles only): depth field = B.DEPTH_COMPACT
+COMPACT_SHAPES = [(16, 16, B.DEPTH_COMPACT), (8, 16, B.DEPTH_COMPACT), (16, 8, B.DEPTH_COMPACT),
+                  (8, 8, B.DEPTH_COMPACT), (4, 16, B.DEPTH_COMPACT)]
 GRIDS = [0, 1, 2, B.GRID_ONE_PER_TILE]
 KIND_SINGLE, KIND_BATCHED = 0, 1
 
@@ -61,8 +65,8 @@ def _dtype(torch, eb):
     return {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}[eb] if eb != 16 else torch.int32
 
 
-def _candidates():
-    for sh in SHAPES:
+def _candidates(kind: int = 0):
+    for sh in SHAPES + (COMPACT_SHAPES if kind == KIND_SINGLE else []):
         for g in GRIDS:
             yield sh + (g,)
 
@@ -80,7 +84,7 @@ def tune_single(torch, bs, elem_bytes: int, size_bits: int, rounds: int, iters: 
     y = torch.empty_like(x)
     xl, yl = x[:lo], y[:lo]
     best = None
-    for cfg in _candidates():
+    for cfg in _candidates(KIND_SINGLE):
         if B.bs_set_config(*cfg) != B.BS_OK:
             continue
         ms = _time(torch, lambda: bs.shuffle(x, 7, rounds, out=y), iters)
@@ -112,7 +116,7 @@ def tune_batched(torch, bs, elem_bytes: int, size_bits: int, rounds: int, iters:
     sd = torch.from_numpy(seeds.view(np.int64)).to(device)
     real_bits = int(np.ceil(np.log2(max(1, -(-total // count)))))
     best = None
-    for cfg in _candidates():
+    for cfg in _candidates(KIND_BATCHED):
         if B.bs_set_config(*cfg) != B.BS_OK:
             continue
         ms = _time(torch, lambda: bs.shuffle_batched(x, off, sd, rounds, out=y), iters)

@@ -141,6 +141,7 @@ def bs_workspace_error(workspace, stream) -> int:
 
 
 GRID_ONE_PER_TILE = 1000
+DEPTH_COMPACT = 8  # tile schedule: kept images compacted through LDS (single shuffles)
 
 
 def bs_set_config(waves: int, items: int, depth: int, grid_mult: int) -> int:

@@ -14,6 +14,9 @@
 #include "bshuffle_probe.h"
 #include "kernels.h"
 
+static_assert(BS_GRID_ONE_PER_TILE == bsd::kGridOnePerTile, "grid constant of the ABI");
+static_assert(BS_DEPTH_COMPACT == bsd::kDepthCompact, "schedule constant of the ABI");
+
 namespace {
 
 thread_local int32_t g_last_hip_error = 0;
@@ -281,6 +284,7 @@ bs_status bs_query_config(uint32_t kind, uint32_t elem_bytes, uint64_t items, ui
   const uint32_t bits = kind == 0 ? bs_domain_bits(items) : ceil_log2((items + num_segments - 1) / num_segments);
   bsd::LaunchConfig c = pick_config(kind, elem_bytes, bits);
   if (kind == 0 && bits > 32) c = {bsd::kWideWaves, bsd::kWideItems, 1, c.grid_mult};
+  if (kind == 1) c = bsd::batch_config(c);
   *waves = c.waves;
   *items_per_lane = c.items;
   *depth = c.depth;
@@ -369,7 +373,7 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
 
   std::lock_guard<std::mutex> lock(g_mu);
   const bsd::LaunchConfig cfg =
-      pick_config(1, elem_bytes, ceil_log2((total_items + num_segments - 1) / num_segments));
+      bsd::batch_config(pick_config(1, elem_bytes, ceil_log2((total_items + num_segments - 1) / num_segments)));
   void* ws = nullptr;
   bs_status st = resolve_workspace(workspace, workspace_bytes, lay.total, s, &ws);
   if (st != BS_OK) return st;

@@ -60,11 +60,13 @@ struct BatchArgs {
 struct LaunchConfig {
   uint32_t waves;      // wavefronts per workgroup
   uint32_t items;      // indices per lane per tile
-  uint32_t depth;      // tiles a workgroup keeps in flight (1 or 2)
+  uint32_t depth;      // tile schedule: 1 or 2 tiles in flight with the kept records in
+                       // registers, or kDepthCompact (kept images compacted through LDS)
   uint32_t grid_mult;  // 0: as many workgroups as stay resident (persistent);
                        // 1..64: that many per CU; kGridOnePerTile: one per tile
 };
 constexpr uint32_t kGridOnePerTile = 1000;
+constexpr uint32_t kDepthCompact = 8;
 
 hipError_t launch_single(const SingleArgs& a, uint32_t elem_bytes, bool nontemporal, const LaunchConfig& cfg,
                          uint32_t num_cus, hipStream_t stream);
@@ -78,6 +80,10 @@ hipError_t launch_tile_prefix(const uint64_t* counts, uint64_t* prefix, uint32_t
 hipError_t launch_cipher_table(const SingleArgs& a, uint32_t* table, hipStream_t stream);
 
 bool config_supported(const LaunchConfig& cfg);
+// Batched launches have no compacted schedule: a compacted shape runs the
+// register schedule with one tile in flight (the default shape if that one is
+// not compiled).  The tile size follows the returned shape.
+LaunchConfig batch_config(const LaunchConfig& cfg);
 
 using SingleFn = void (*)(SingleArgs);
 using BatchFn = void (*)(BatchArgs);
@@ -86,6 +92,8 @@ using BatchFn = void (*)(BatchArgs);
 // Tile shapes that are compiled: (waves per workgroup, indices per lane, depth).
 #define BSD_FOR_EACH_SHAPE(X) \
   X(4, 16, 2) X(8, 16, 2) X(8, 16, 1) X(16, 16, 1) X(16, 8, 1) X(8, 8, 2) X(4, 16, 1) X(16, 16, 2) X(16, 8, 2)
+// Shapes of the LDS-compacted schedule (single shuffles, k <= 32): (waves, items).
+#define BSD_FOR_EACH_COMPACT_SHAPE(X) X(16, 16) X(8, 16) X(16, 8) X(8, 8) X(4, 16)
 // Shape used when the index space needs 64 bits (k > 32).
 constexpr uint32_t kWideWaves = 8, kWideItems = 16;
 

@@ -40,23 +40,41 @@ template <> struct Payload<0> { using T = uint32_t; };  // no payload (cipher + 
 template <> struct Payload<1> { using T = uint8_t; };
 template <> struct Payload<2> { using T = uint16_t; };
 template <> struct Payload<4> { using T = uint32_t; };
-template <> struct Payload<8> { using T = u32x2; };
-template <> struct Payload<16> { using T = u32x4; };
+template <> struct Payload<8> { using T = uint64_t; };
+// 16-byte records: two 64-bit halves (an ext_vector of four words would be
+// merged by the compiler with its neighbours in a register array into one
+// wide vector value, which spills)
+struct alignas(16) Rec16 { uint64_t lo, hi; };
+template <> struct Payload<16> { using T = Rec16; };
 
 template <int EB>
 __device__ __forceinline__ typename Payload<EB>::T load_record(const uint8_t* __restrict__ base, uint64_t idx) {
   using T = typename Payload<EB>::T;
-  return *reinterpret_cast<const T*>(base + idx * uint64_t(EB));
+  if constexpr (EB == 16) {
+    const u32x4 w = *reinterpret_cast<const u32x4*>(base + idx * 16u);
+    return Rec16{uint64_t(w.x) | (uint64_t(w.y) << 32), uint64_t(w.z) | (uint64_t(w.w) << 32)};
+  } else {
+    return *reinterpret_cast<const T*>(base + idx * uint64_t(EB));
+  }
 }
 
 template <int EB, bool NT>
 __device__ __forceinline__ void store_record(uint8_t* __restrict__ base, uint64_t idx, typename Payload<EB>::T v) {
-  using T = typename Payload<EB>::T;
-  T* p = reinterpret_cast<T*>(base + idx * uint64_t(EB));
-  if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
+  if constexpr (EB == 16) {
+    u32x4* p = reinterpret_cast<u32x4*>(base + idx * 16u);
+    const u32x4 w = {uint32_t(v.lo), uint32_t(v.lo >> 32), uint32_t(v.hi), uint32_t(v.hi >> 32)};
+    if constexpr (NT)
+      __builtin_nontemporal_store(w, p);
+    else
+      *p = w;
+  } else {
+    using T = typename Payload<EB>::T;
+    T* p = reinterpret_cast<T*>(base + idx * uint64_t(EB));
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
+  }
 }
 
 // ------------------------------------------------------ workgroup state --
@@ -299,12 +317,12 @@ __device__ __forceinline__ void tile_store(const PendingTile<EB, MODE, ITEMS, WI
 // DEPTH 1 finishes each tile before starting the next (fewer registers).
 // Minimum waves per SIMD the register budget is sized for (HIP's second
 // launch-bounds argument).
-template <int WAVES, int DEPTH>
-constexpr int kMinWavesPerSimd = 1;
+template <int EB, int ITEMS, int DEPTH>
+constexpr int kMinWavesPerSimd = (ITEMS <= 8 && DEPTH == 1 && EB <= 4) ? 8 : 1;
 
 template <int EB, bool ODD, int WAVES, int ITEMS, int DEPTH, bool WIDE, int MODE = kGather, bool LOOKBACK = true,
           int BIJ = kBijPhilox>
-__global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void shuffle_single_kernel(
+__global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) void shuffle_single_kernel(
     const SingleArgs a) {
   __shared__ TileLds<WAVES> lds;
   group_begin(a.hdr, lds);
@@ -345,6 +363,112 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void 
     }
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds);
+}
+
+// ------------------------------------------------ LDS-compacted tiles --
+// Second tile schedule (narrow domains, k <= 32).  The register schedule above
+// issues each item step's gathers and stores with only the kept lanes active:
+// when about half the padded indices are rejected, twice as many half-empty
+// memory instructions run as kept records need.  Here the kept images of a
+// tile are first written to LDS in rank order; the workgroup's threads then
+// gather and store consecutive ranks, so every memory instruction runs with
+// all lanes active and each wavefront's stores cover 64 consecutive records.
+// Per tile:
+//   1. cipher and keep flags (ITEMS images per lane held in registers);
+//   2. wave counts -> LDS -> wave offsets; kept images written to LDS at
+//      their tile-local ranks; the next ticket is taken;
+//   3. thread t gathers ranks t, t + T, t + 2T, ... (T threads) from in[];
+//   4. wavefront 0 runs the look-back while those loads are in flight;
+//   5. rank p is stored at out[prefix + p].
+template <int WAVES, int ITEMS>
+struct CompactLds {
+  TileLds<WAVES> t;
+  uint32_t y[64 * WAVES * ITEMS];  // kept images of the tile, in rank order
+};
+
+template <int EB, bool ODD, int WAVES, int ITEMS, int BIJ>
+__device__ __forceinline__ void compact_tile(uint32_t tile, const SingleArgs& a, uint32_t tag, bool nt,
+                                             CompactLds<WAVES, ITEMS>& lds) {
+  using T = typename Payload<EB>::T;
+  constexpr uint32_t kThreads = 64u * WAVES;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  PendingTile<4, kIndices, ITEMS, false> c;
+  tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile,
+                                                         a.table, a.lcg_a, a.lcg_c);
+  if (lane == 0) lds.t.wave_count[wave] = c.wave_count;
+  __syncthreads();
+  uint32_t pos = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    const uint32_t cnt = lds.t.wave_count[w];
+    pos += (uint32_t(w) < wave) ? cnt : 0u;
+    total += cnt;
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const bool keep = (c.keep_bits >> j) & 1u;
+    const uint64_t m = __ballot(keep);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    if (keep) lds.y[pos + below] = c.val[j];
+    pos += uint32_t(__builtin_popcountll(m));
+  }
+  constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
+  if (wave == kTicketWave && lane == 0) lds.t.next_ticket = atomicAdd(&a.hdr->ticket, 1u);
+  __syncthreads();
+  // gathers for ranks threadIdx.x + q * kThreads, issued before the look-back;
+  // lanes past the last rank re-read the last kept record (no per-lane branch,
+  // so the payload registers stay independent values)
+  const uint32_t steps = (total + kThreads - 1) / kThreads;
+  T v[ITEMS];
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    if (uint32_t(q) < steps) {
+      const uint32_t p = min(threadIdx.x + uint32_t(q) * kThreads, total - 1);
+      v[q] = load_record<EB>(a.in, lds.y[p]);
+    }
+  }
+  if (wave == 0) {
+    const uint64_t ex = lookback_exclusive_prefix(a.status, 0u, tile, tag, uint64_t(total), &a.hdr->error);
+    if (lane == 0) lds.t.tile_exclusive = ex;
+  }
+  __syncthreads();
+  const uint64_t prefix = lds.t.tile_exclusive;
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    const uint32_t p = threadIdx.x + uint32_t(q) * kThreads;
+    // ranks are < n by construction; the bound only keeps a timed-out
+    // look-back from writing outside the buffer
+    if (uint32_t(q) < steps && p < total && prefix + p < a.n) {
+      if (nt)
+        store_record<EB, true>(a.out, prefix + p, v[q]);
+      else
+        store_record<EB, false>(a.out, prefix + p, v[q]);
+    }
+  }
+}
+
+// Waves per SIMD the compacted kernel's register budget is sized for: with 8
+// indices per lane and records of at most 4 bytes, two 16-wave workgroups fit
+// on a CU (64 VGPRs), so one can compute while the other waits at a barrier or
+// on the look-back.
+template <int EB, int ITEMS>
+constexpr int kCompactMinWaves = (ITEMS <= 8 && EB <= 4) ? 8 : 1;
+
+template <int EB, bool ODD, int WAVES, int ITEMS, int BIJ = kBijPhilox>
+__global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shuffle_compact_kernel(
+    const SingleArgs a) {
+  __shared__ CompactLds<WAVES, ITEMS> lds;
+  group_begin(a.hdr, lds.t);
+  const uint32_t gen = lds.t.gen;
+  const uint32_t tag = gen & kTagMask;
+  const bool nt = a.nontemporal != 0;
+  uint32_t tile = lds.t.ticket;
+  while (tile < a.num_tiles) {
+    compact_tile<EB, ODD, WAVES, ITEMS, BIJ>(tile, a, tag, nt, lds);
+    tile = lds.t.next_ticket;
+  }
+  group_end(a.hdr, a.status, a.capacity, gen, lds.t);
 }
 
 // First pass of the two-pass scan variant: the kept count of every tile,
@@ -428,7 +552,7 @@ __device__ __forceinline__ void batch_gather(PendingTile<EB, kGather, ITEMS, fal
 }
 
 template <int EB, int WAVES, int ITEMS, int DEPTH>
-__global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<WAVES, DEPTH>)) void shuffle_batched_kernel(
+__global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) void shuffle_batched_kernel(
     const BatchArgs a) {
   __shared__ TileLds<WAVES> lds;
   group_begin(a.hdr, lds);
@@ -512,6 +636,13 @@ SingleFn pick_single_shape(const LaunchConfig& c) {
   if constexpr (WIDE) {
     return &shuffle_single_kernel<EB, ODD, 8, 16, 1, true>;
   } else {
+    if (c.depth == kDepthCompact) {
+#define BSD_PICK(W, I) \
+  if (c.waves == W && c.items == I) return &shuffle_compact_kernel<EB, ODD, W, I>;
+      BSD_FOR_EACH_COMPACT_SHAPE(BSD_PICK)
+#undef BSD_PICK
+      return nullptr;
+    }
 #define BSD_PICK(W, I, D) \
   if (c.waves == W && c.items == I && c.depth == D) return &shuffle_single_kernel<EB, ODD, W, I, D, false>;
     BSD_FOR_EACH_SHAPE(BSD_PICK)

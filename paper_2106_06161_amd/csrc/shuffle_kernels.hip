@@ -108,6 +108,10 @@ bool config_supported(const LaunchConfig& c) {
   if (c.waves == W && c.items == I && c.depth == D) return true;
   BSD_FOR_EACH_SHAPE(BSD_MATCH)
 #undef BSD_MATCH
+#define BSD_MATCH(W, I) \
+  if (c.waves == W && c.items == I && c.depth == kDepthCompact) return true;
+  BSD_FOR_EACH_COMPACT_SHAPE(BSD_MATCH)
+#undef BSD_MATCH
   return false;
 }
 
@@ -160,6 +164,13 @@ hipError_t launch_single(const SingleArgs& a0, uint32_t eb, bool nt, const Launc
   const uint32_t grid = grid_for(a.num_tiles, cfg, num_cus, reinterpret_cast<const void*>(fn));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * 64), 0, stream, a);
   return hipGetLastError();
+}
+
+LaunchConfig batch_config(const LaunchConfig& c) {
+  LaunchConfig b = c;
+  if (b.depth == kDepthCompact) b.depth = 1;
+  if (!config_supported(b)) b = {16, 16, 1, c.grid_mult};
+  return b;
 }
 
 hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& cfg, uint32_t num_cus,

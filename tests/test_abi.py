@@ -96,8 +96,25 @@ def test_config_round_trip():
     assert B.bs_set_config(8, 8, 1, 0) == B.BS_EINVAL
     assert B.bs_set_config(8, 16, 1, 65) == B.BS_EINVAL
     assert B.bs_set_config(8, 16, 1, B.GRID_ONE_PER_TILE) == B.BS_OK
+    assert B.bs_set_config(16, 8, B.DEPTH_COMPACT, 0) == B.BS_OK
+    assert B.bs_get_config() == (16, 8, B.DEPTH_COMPACT, 0)
+    assert B.bs_set_config(16, 4, B.DEPTH_COMPACT, 0) == B.BS_EINVAL
     assert B.bs_set_config(0, 0, 0, 0) == B.BS_OK
     assert B.bs_get_config() == before
+
+
+def test_compact_shape_maps_to_register_schedule_for_batches():
+    """A forced compacted shape applies to single shuffles; batched launches
+    report (and run) the register schedule with the same tile."""
+    try:
+        assert B.bs_set_config(16, 8, B.DEPTH_COMPACT, 0) == B.BS_OK
+        assert B.bs_query_config(0, 4, 1 << 20) == (16, 8, B.DEPTH_COMPACT, 0)
+        assert B.bs_query_config(1, 4, 1 << 20, 16) == (16, 8, 1, 0)
+        assert B.bs_set_config(8, 8, B.DEPTH_COMPACT, 0) == B.BS_OK
+        assert B.bs_query_config(1, 4, 1 << 20, 16) == (16, 16, 1, 0)  # (8, 8, 1) is not compiled
+        assert B.bs_query_config(0, 4, (1 << 32) + 1) == (8, 16, 1, 0)  # 64-bit index path
+    finally:
+        B.bs_set_config(0, 0, 0, 0)
 
 
 def test_probe_argument_checks():

@@ -76,8 +76,11 @@ def test_element_sizes(eb_dtype, width, n):
     assert np.array_equal(gpu(x, 77, 24), oracle.shuffle(x, 77, 24))
 
 
-SHAPES = [(4, 16, 2), (8, 16, 2), (8, 16, 1), (16, 16, 1), (16, 8, 1), (8, 8, 2), (4, 16, 1)]
-CONFIGS = [s + (0,) for s in SHAPES] + [(8, 16, 2, 1), (4, 16, 1, 1000), (16, 8, 1, 3)]
+SHAPES = [(4, 16, 2), (8, 16, 2), (8, 16, 1), (16, 16, 1), (16, 8, 1), (8, 8, 2), (4, 16, 1), (16, 16, 2),
+          (16, 8, 2)]
+COMPACT = [(16, 16, 8), (8, 16, 8), (16, 8, 8), (8, 8, 8), (4, 16, 8)]  # LDS-compacted schedule
+CONFIGS = [s + (0,) for s in SHAPES + COMPACT] + [(8, 16, 2, 1), (4, 16, 1, 1000), (16, 8, 1, 3),
+                                                  (16, 16, 8, 1000), (8, 16, 8, 1)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
@@ -87,6 +90,17 @@ def test_launch_configs_do_not_change_output(cfg, rounds):
     for n in (300_001, 262_144, 33):
         x = W.uniform_u32(n, seed=3)
         assert np.array_equal(gpu(x, 9, rounds), oracle.shuffle(x, 9, rounds)), (cfg, n)
+
+
+@pytest.mark.parametrize("cfg", [(16, 16, 8, 0), (8, 8, 8, 0)])
+def test_compact_schedule_element_sizes(cfg):
+    assert B.bs_set_config(*cfg) == B.BS_OK
+    rng = np.random.default_rng(8)
+    for dt, width in ((np.uint8, 0), (np.uint16, 0), (np.uint64, 0), (np.float32, 4)):
+        for n in (17, 16_385, 200_003):
+            shape = (n,) if width == 0 else (n, width)
+            x = rng.integers(0, 250, size=shape).astype(dt)
+            assert np.array_equal(gpu(x, 12, 24), oracle.shuffle(x, 12, 24)), (cfg, dt, n)
 
 
 def test_store_modes_agree():
