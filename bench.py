@@ -64,8 +64,9 @@ def kernel_source_digest() -> str:
 
 def kernel_label(launch: dict) -> str:
     """The fused kernel that runs the headline step (even k, 32-bit indices)."""
-    if launch["depth"] == 8:  # kept images compacted through LDS
-        return "bsd::shuffle_compact_kernel<4, false, {waves}, {items}, 0>".format(**launch)
+    if launch["depth"] in (8, 9):  # kept images compacted through LDS (9: pipelined cipher)
+        pipe = "true" if launch["depth"] == 9 else "false"
+        return "bsd::shuffle_compact_kernel<4, false, {waves}, {items}, ".format(**launch) + pipe + ", 0, true>"
     return "bsd::shuffle_single_kernel<4, false, {waves}, {items}, {depth}, false>".format(**launch)
 
 

@@ -185,13 +185,15 @@ bs_status bs_shuffle_lcg(const void *in, void *out, uint64_t n, uint32_t elem_by
 /*
  * Launch configuration (never changes results).  A tile is waves x 64 x items
  * padded indices; depth selects the tile schedule: 1 or 2 tiles in flight per
- * workgroup with the kept records held in registers, or BS_DEPTH_COMPACT, where
- * a tile's kept images are first compacted in LDS and then gathered and stored
- * by all lanes in rank order (single shuffles with k <= 32; batched launches
- * run such a shape with depth 1).
+ * workgroup with the kept records held in registers; BS_DEPTH_COMPACT, where a
+ * tile's kept images are first compacted in LDS and then gathered and stored
+ * by all lanes in rank order; or BS_DEPTH_COMPACT_PIPE, the same with the next
+ * tile's cipher computed while the current tile's gathers are in flight.  The
+ * compacted schedules serve single shuffles with k <= 32; batched launches run
+ * such a shape with depth 1.
  * Compiled shapes (waves, items, depth): (4,16,2) (8,16,2) (8,16,1)
- * (16,16,1) (16,8,1) (8,8,2) (4,16,1) (16,16,2) (16,8,2), and with
- * BS_DEPTH_COMPACT (16,16) (8,16) (16,8) (8,8) (4,16).  grid_mult: 0 = a persistent grid of
+ * (16,16,1) (16,8,1) (8,8,2) (4,16,1) (16,16,2) (16,8,2), and with either
+ * compacted schedule (16,16) (8,16) (16,8) (8,8) (4,16).  grid_mult: 0 = a persistent grid of
  * as many workgroups as the device keeps resident, 1..64 = that many
  * workgroups per CU, BS_GRID_ONE_PER_TILE = one workgroup per tile.
  * bs_set_config with a shape forces it for every later call (from every
@@ -201,6 +203,7 @@ bs_status bs_shuffle_lcg(const void *in, void *out, uint64_t n, uint32_t elem_by
  */
 #define BS_GRID_ONE_PER_TILE 1000u
 #define BS_DEPTH_COMPACT 8u
+#define BS_DEPTH_COMPACT_PIPE 9u
 bs_status bs_set_config(uint32_t waves_per_group, uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
 bs_status bs_get_config(uint32_t *waves_per_group, uint32_t *items_per_lane, uint32_t *depth,
                         uint32_t *grid_mult);

@@ -21,9 +21,10 @@ from . import binding as B
 
 TUNED_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_configs.json")
 SHAPES = [(4, 16, 2), (8, 16, 2), (8, 16, 1), (16, 16, 1), (16, 8, 1), (8, 8, 2), (4, 16, 1), (16, 16, 2), (16, 8, 2)]
-# LDS-compacted schedule (single shuffles only): depth field = B.DEPTH_COMPACT
-COMPACT_SHAPES = [(16, 16, B.DEPTH_COMPACT), (8, 16, B.DEPTH_COMPACT), (16, 8, B.DEPTH_COMPACT),
-                  (8, 8, B.DEPTH_COMPACT), (4, 16, B.DEPTH_COMPACT)]
+# LDS-compacted schedules (single shuffles only): depth field = B.DEPTH_COMPACT or
+# B.DEPTH_COMPACT_PIPE
+COMPACT_SHAPES = [(w, i, d) for d in (B.DEPTH_COMPACT, B.DEPTH_COMPACT_PIPE)
+                  for (w, i) in ((16, 16), (8, 16), (16, 8), (8, 8), (4, 16))]
 GRIDS = [0, 1, 2, B.GRID_ONE_PER_TILE]
 KIND_SINGLE, KIND_BATCHED = 0, 1
 

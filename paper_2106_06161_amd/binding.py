@@ -142,6 +142,7 @@ def bs_workspace_error(workspace, stream) -> int:
 
 GRID_ONE_PER_TILE = 1000
 DEPTH_COMPACT = 8  # tile schedule: kept images compacted through LDS (single shuffles)
+DEPTH_COMPACT_PIPE = 9  # same, with the next tile's cipher overlapping the current tile's gathers
 
 
 def bs_set_config(waves: int, items: int, depth: int, grid_mult: int) -> int:

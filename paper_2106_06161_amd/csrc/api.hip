@@ -16,6 +16,7 @@
 
 static_assert(BS_GRID_ONE_PER_TILE == bsd::kGridOnePerTile, "grid constant of the ABI");
 static_assert(BS_DEPTH_COMPACT == bsd::kDepthCompact, "schedule constant of the ABI");
+static_assert(BS_DEPTH_COMPACT_PIPE == bsd::kDepthCompactPipe, "schedule constant of the ABI");
 
 namespace {
 

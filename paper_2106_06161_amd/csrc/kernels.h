@@ -61,12 +61,14 @@ struct LaunchConfig {
   uint32_t waves;      // wavefronts per workgroup
   uint32_t items;      // indices per lane per tile
   uint32_t depth;      // tile schedule: 1 or 2 tiles in flight with the kept records in
-                       // registers, or kDepthCompact (kept images compacted through LDS)
+                       // registers, or kDepthCompact / kDepthCompactPipe (kept images
+                       // compacted through LDS)
   uint32_t grid_mult;  // 0: as many workgroups as stay resident (persistent);
                        // 1..64: that many per CU; kGridOnePerTile: one per tile
 };
 constexpr uint32_t kGridOnePerTile = 1000;
-constexpr uint32_t kDepthCompact = 8;
+constexpr uint32_t kDepthCompact = 8;      // kept images compacted through LDS
+constexpr uint32_t kDepthCompactPipe = 9;  // same, next tile's cipher overlapping the gathers
 
 hipError_t launch_single(const SingleArgs& a, uint32_t elem_bytes, bool nontemporal, const LaunchConfig& cfg,
                          uint32_t num_cus, hipStream_t stream);

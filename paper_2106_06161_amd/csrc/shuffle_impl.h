@@ -386,16 +386,22 @@ struct CompactLds {
   uint32_t y[64 * WAVES * ITEMS];  // kept images of the tile, in rank order
 };
 
-template <int EB, bool ODD, int WAVES, int ITEMS, int BIJ>
-__device__ __forceinline__ void compact_tile(uint32_t tile, const SingleArgs& a, uint32_t tag, bool nt,
-                                             CompactLds<WAVES, ITEMS>& lds) {
+// Compacts the tile whose images are in c into LDS, issues its gathers, runs
+// its look-back and stores it.  With PIPE, the cipher of the next tile (taken
+// from the ticket counter during the compaction) runs between the gathers and
+// the stores, so its VALU work covers the gathers' latency; c then holds the
+// next tile's images on return.  Returns the next tile.
+template <int EB, bool ODD, int WAVES, int ITEMS, int BIJ, bool PIPE, bool LOOKBACK>
+__device__ __forceinline__ uint32_t compact_tile(uint32_t tile, PendingTile<4, kIndices, ITEMS, false>& c,
+                                                 const SingleArgs& a, uint32_t tag, bool nt,
+                                                 CompactLds<WAVES, ITEMS>& lds) {
   using T = typename Payload<EB>::T;
   constexpr uint32_t kThreads = 64u * WAVES;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  PendingTile<4, kIndices, ITEMS, false> c;
-  tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile,
-                                                         a.table, a.lcg_a, a.lcg_c);
+  if constexpr (!PIPE)
+    tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile,
+                                                           a.table, a.lcg_a, a.lcg_c);
   if (lane == 0) lds.t.wave_count[wave] = c.wave_count;
   __syncthreads();
   uint32_t pos = 0, total = 0;
@@ -416,6 +422,7 @@ __device__ __forceinline__ void compact_tile(uint32_t tile, const SingleArgs& a,
   constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
   if (wave == kTicketWave && lane == 0) lds.t.next_ticket = atomicAdd(&a.hdr->ticket, 1u);
   __syncthreads();
+  const uint32_t next = lds.t.next_ticket;
   // gathers for ranks threadIdx.x + q * kThreads, issued before the look-back;
   // lanes past the last rank re-read the last kept record (no per-lane branch,
   // so the payload registers stay independent values)
@@ -429,8 +436,17 @@ __device__ __forceinline__ void compact_tile(uint32_t tile, const SingleArgs& a,
     }
   }
   if (wave == 0) {
-    const uint64_t ex = lookback_exclusive_prefix(a.status, 0u, tile, tag, uint64_t(total), &a.hdr->error);
+    uint64_t ex;
+    if constexpr (LOOKBACK)
+      ex = lookback_exclusive_prefix(a.status, 0u, tile, tag, uint64_t(total), &a.hdr->error);
+    else
+      ex = a.tile_prefix[tile];  // written by an earlier scan pass
     if (lane == 0) lds.t.tile_exclusive = ex;
+  }
+  if constexpr (PIPE) {
+    if (next < a.num_tiles)
+      tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, next,
+                                                             a.table, a.lcg_a, a.lcg_c);
   }
   __syncthreads();
   const uint64_t prefix = lds.t.tile_exclusive;
@@ -446,6 +462,7 @@ __device__ __forceinline__ void compact_tile(uint32_t tile, const SingleArgs& a,
         store_record<EB, false>(a.out, prefix + p, v[q]);
     }
   }
+  return next;
 }
 
 // Waves per SIMD the compacted kernel's register budget is sized for: with 8
@@ -455,7 +472,7 @@ __device__ __forceinline__ void compact_tile(uint32_t tile, const SingleArgs& a,
 template <int EB, int ITEMS>
 constexpr int kCompactMinWaves = (ITEMS <= 8 && EB <= 4) ? 8 : 1;
 
-template <int EB, bool ODD, int WAVES, int ITEMS, int BIJ = kBijPhilox>
+template <int EB, bool ODD, int WAVES, int ITEMS, bool PIPE, int BIJ = kBijPhilox, bool LOOKBACK = true>
 __global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shuffle_compact_kernel(
     const SingleArgs a) {
   __shared__ CompactLds<WAVES, ITEMS> lds;
@@ -464,10 +481,13 @@ __global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shu
   const uint32_t tag = gen & kTagMask;
   const bool nt = a.nontemporal != 0;
   uint32_t tile = lds.t.ticket;
-  while (tile < a.num_tiles) {
-    compact_tile<EB, ODD, WAVES, ITEMS, BIJ>(tile, a, tag, nt, lds);
-    tile = lds.t.next_ticket;
+  PendingTile<4, kIndices, ITEMS, false> c;
+  if constexpr (PIPE) {
+    if (tile < a.num_tiles)
+      tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile,
+                                                             a.table, a.lcg_a, a.lcg_c);
   }
+  while (tile < a.num_tiles) tile = compact_tile<EB, ODD, WAVES, ITEMS, BIJ, PIPE, LOOKBACK>(tile, c, a, tag, nt, lds);
   group_end(a.hdr, a.status, a.capacity, gen, lds.t);
 }
 
@@ -614,7 +634,7 @@ SingleFn pick_variant_eb(bool odd, bool wide) {
                : &shuffle_single_kernel<EB, false, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>;
   } else if constexpr (BIJ == kBijLcg) {  // no Feistel halves: odd and even k share a kernel
     if (wide) return &shuffle_single_kernel<EB, false, kWideWaves, kWideItems, 1, true, MODE, LOOKBACK, BIJ>;
-    return &shuffle_single_kernel<EB, false, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>;
+    return &shuffle_compact_kernel<EB, false, kAltWaves, kAltItems, true, BIJ, LOOKBACK>;
   } else {
     if (wide) {
       if constexpr (!LOOKBACK) return nullptr;
@@ -622,6 +642,9 @@ SingleFn pick_variant_eb(bool odd, bool wide) {
       return odd ? &shuffle_single_kernel<EB, true, kWideWaves, kWideItems, 1, true, MODE, LOOKBACK, BIJ>
                  : &shuffle_single_kernel<EB, false, kWideWaves, kWideItems, 1, true, MODE, LOOKBACK, BIJ>;
     }
+    if constexpr (MODE == kGather)  // the two-pass form: same tile schedule as the fused kernel
+      return odd ? &shuffle_compact_kernel<EB, true, kAltWaves, kAltItems, true, BIJ, LOOKBACK>
+                 : &shuffle_compact_kernel<EB, false, kAltWaves, kAltItems, true, BIJ, LOOKBACK>;
     return odd ? &shuffle_single_kernel<EB, true, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>
                : &shuffle_single_kernel<EB, false, kAltWaves, kAltItems, 1, false, MODE, LOOKBACK, BIJ>;
   }
@@ -636,9 +659,11 @@ SingleFn pick_single_shape(const LaunchConfig& c) {
   if constexpr (WIDE) {
     return &shuffle_single_kernel<EB, ODD, 8, 16, 1, true>;
   } else {
-    if (c.depth == kDepthCompact) {
-#define BSD_PICK(W, I) \
-  if (c.waves == W && c.items == I) return &shuffle_compact_kernel<EB, ODD, W, I>;
+    if (c.depth == kDepthCompact || c.depth == kDepthCompactPipe) {
+      const bool pipe = c.depth == kDepthCompactPipe;
+#define BSD_PICK(W, I)                  \
+  if (c.waves == W && c.items == I)     \
+    return pipe ? &shuffle_compact_kernel<EB, ODD, W, I, true> : &shuffle_compact_kernel<EB, ODD, W, I, false>;
       BSD_FOR_EACH_COMPACT_SHAPE(BSD_PICK)
 #undef BSD_PICK
       return nullptr;

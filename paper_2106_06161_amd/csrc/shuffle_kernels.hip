@@ -109,7 +109,7 @@ bool config_supported(const LaunchConfig& c) {
   BSD_FOR_EACH_SHAPE(BSD_MATCH)
 #undef BSD_MATCH
 #define BSD_MATCH(W, I) \
-  if (c.waves == W && c.items == I && c.depth == kDepthCompact) return true;
+  if (c.waves == W && c.items == I && (c.depth == kDepthCompact || c.depth == kDepthCompactPipe)) return true;
   BSD_FOR_EACH_COMPACT_SHAPE(BSD_MATCH)
 #undef BSD_MATCH
   return false;
@@ -168,7 +168,7 @@ hipError_t launch_single(const SingleArgs& a0, uint32_t eb, bool nt, const Launc
 
 LaunchConfig batch_config(const LaunchConfig& c) {
   LaunchConfig b = c;
-  if (b.depth == kDepthCompact) b.depth = 1;
+  if (b.depth == kDepthCompact || b.depth == kDepthCompactPipe) b.depth = 1;
   if (!config_supported(b)) b = {16, 16, 1, c.grid_mult};
   return b;
 }

@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import sys
 import time
 from collections import deque
 from typing import Callable, Protocol
@@ -111,6 +112,43 @@ class ServeReport:
         }
 
 
+class _Grouper:
+    """Admitted requests on their way to launches: a request above small_items
+    is a launch of its own; smaller ones are coalesced per element size, in
+    admission order, up to max_requests requests and max_items records per
+    launch.  Closed groups wait in `ready` (FIFO); flush() closes the open ones.
+    Every operation is O(1) per request."""
+
+    def __init__(self, small_items: int, max_requests: int, max_items: int):
+        self.small_items, self.max_requests, self.max_items = small_items, max_requests, max_items
+        self.ready: deque[list[Request]] = deque()
+        self.open: dict[int, list[Request]] = {}
+        self.open_items: dict[int, int] = {}
+
+    def add(self, r: Request) -> None:
+        if r.n > self.small_items:
+            self.ready.append([r])
+            return
+        eb = r.elem_bytes
+        cur = self.open.setdefault(eb, [])
+        if cur and (len(cur) >= self.max_requests or self.open_items[eb] + r.n > self.max_items):
+            self.ready.append(cur)
+            cur = self.open[eb] = []
+            self.open_items[eb] = 0
+        cur.append(r)
+        self.open_items[eb] = self.open_items.get(eb, 0) + r.n
+
+    def flush(self) -> None:
+        for eb, cur in self.open.items():
+            if cur:
+                self.ready.append(cur)
+        self.open.clear()
+        self.open_items.clear()
+
+    def __bool__(self) -> bool:
+        return bool(self.ready) or any(self.open.values())
+
+
 class ShuffleServer:
     def __init__(self, executor: Executor, budget_bytes: int, small_items: int = 1 << 20,
                  max_batch_requests: int = 2048, max_batch_items: int = 1 << 26, max_inflight: int = 16,
@@ -129,34 +167,16 @@ class ShuffleServer:
         """Drop a request that has not been admitted yet."""
         self.cancelled.add(request_id)
 
-    def _groups(self, ready: list[Request]) -> list[list[Request]]:
-        """Split admitted requests into launches: big ones alone, small ones
-        coalesced per element size (in admission order)."""
-        groups: list[list[Request]] = []
-        small: dict[int, list[Request]] = {}
-        for r in ready:
-            if r.n > self.small_items:
-                groups.append([r])
-                continue
-            cur = small.setdefault(r.elem_bytes, [])
-            if cur and (len(cur) >= self.max_batch_requests or
-                        sum(q.n for q in cur) + r.n > self.max_batch_items):
-                groups.append(cur)
-                cur = small[r.elem_bytes] = []
-            cur.append(r)
-        groups.extend(g for g in small.values() if g)
-        return groups
-
     def run(self, requests: list[Request], on_result: Callable[[Request, object], None] | None = None) -> ServeReport:
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.id)))
-        admitted: list[Request] = []
+        grouper = _Grouper(self.small_items, self.max_batch_requests, self.max_batch_items)
         admit_time: dict[int, float] = {}
         inflight: list[tuple[object, list[Request]]] = []
         completions: list[Completion] = []
         reserved = max_reserved = 0
         launches = batched = 0
         t0 = self.clock()
-        while pending or admitted or inflight:
+        while pending or grouper or inflight:
             now = self.clock() - t0
             # retire finished launches
             still = []
@@ -206,28 +226,26 @@ class ShuffleServer:
                     reserved -= r.out_bytes
                     completions.append(Completion(r, now, self.clock() - t0, 0, f"{type(exc).__name__}: {exc}"))
                     continue
-                admitted.append(r)
-            # launch what is admitted, as slots allow
-            if admitted and len(inflight) < self.max_inflight:
-                groups = self._groups(admitted)
-                admitted = []
-                for g in groups:
-                    if len(inflight) >= self.max_inflight:
-                        admitted.extend(g)
-                        continue
-                    try:
-                        handle = self.ex.launch(g)
-                    except Exception as exc:
-                        t_fail = self.clock() - t0
-                        for r in g:
-                            completions.append(Completion(r, admit_time[r.id], t_fail, len(g),
-                                                          f"{type(exc).__name__}: {exc}"))
-                            reserved -= r.out_bytes
-                        continue
-                    inflight.append((handle, g))
-                    launches += 1
-                    batched += len(g) > 1
-            if not inflight and not admitted and pending:
+                grouper.add(r)
+            # launch what is admitted, as slots allow; open small groups are
+            # closed only when a slot is free for them
+            while grouper and len(inflight) < self.max_inflight:
+                if not grouper.ready:
+                    grouper.flush()
+                g = grouper.ready.popleft()
+                try:
+                    handle = self.ex.launch(g)
+                except Exception as exc:
+                    t_fail = self.clock() - t0
+                    for r in g:
+                        completions.append(Completion(r, admit_time[r.id], t_fail, len(g),
+                                                      f"{type(exc).__name__}: {exc}"))
+                        reserved -= r.out_bytes
+                    continue
+                inflight.append((handle, g))
+                launches += 1
+                batched += len(g) > 1
+            if not inflight and not grouper and pending:
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
                     self.sleep(min(wait, 0.001))
@@ -351,7 +369,9 @@ def main(argv=None) -> int:
     p.add_argument("--requests", type=int, default=2000)
     p.add_argument("--lo", type=int, default=1000)
     p.add_argument("--hi", type=int, default=100_000_000)
-    p.add_argument("--qps", type=float, default=0.0, help="0: measure closed-loop capacity first, run at 0.8x")
+    p.add_argument("--qps", type=float, default=0.0,
+                   help="0: measure closed-loop capacity C first, then run at each of --loads x C")
+    p.add_argument("--loads", default="0.8", help="comma-separated fractions of C (with --qps 0)")
     p.add_argument("--budget-gib", type=float, default=32.0)
     p.add_argument("--streams", type=int, default=4)
     p.add_argument("--rounds", type=int, default=24)
@@ -359,14 +379,20 @@ def main(argv=None) -> int:
     a = p.parse_args(argv)
     ex = HipExecutor(streams=a.streams, rounds=a.rounds)
     server = ShuffleServer(ex, int(a.budget_gib * 2**30))
-    qps = a.qps
-    out = {}
-    if qps <= 0:
+    out = {"requests": a.requests}
+    if a.qps > 0:
+        rates = [a.qps]
+    else:
         cap = server.run(make_requests(a.requests, a.lo, a.hi, 1e12, a.seed)).summary()
         out["closed_loop"] = cap
-        qps = 0.8 * cap["requests_per_s"]
-    rep = server.run(make_requests(a.requests, a.lo, a.hi, qps, a.seed + 1))
-    out["open_loop"] = dict(rep.summary(), qps=qps)
+        print(f"closed loop: {cap['requests_per_s']:.1f} requests/s", file=sys.stderr, flush=True)
+        rates = [float(f) * cap["requests_per_s"] for f in a.loads.split(",")]
+    out["open_loop"] = []
+    for qps in rates:
+        rep = server.run(make_requests(a.requests, a.lo, a.hi, qps, a.seed + 1)).summary()
+        out["open_loop"].append(dict(rep, qps=qps))
+        print(f"open loop at {qps:.1f} requests/s: p50 {rep['latency_p50_ms']:.2f} ms, "
+              f"p99 {rep['latency_p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     out["device_error"] = ex.check_errors()
     print(json.dumps(out))
     return 0

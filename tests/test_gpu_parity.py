@@ -78,9 +78,10 @@ def test_element_sizes(eb_dtype, width, n):
 
 SHAPES = [(4, 16, 2), (8, 16, 2), (8, 16, 1), (16, 16, 1), (16, 8, 1), (8, 8, 2), (4, 16, 1), (16, 16, 2),
           (16, 8, 2)]
-COMPACT = [(16, 16, 8), (8, 16, 8), (16, 8, 8), (8, 8, 8), (4, 16, 8)]  # LDS-compacted schedule
+COMPACT = [(w, i, d) for d in (B.DEPTH_COMPACT, B.DEPTH_COMPACT_PIPE)  # LDS-compacted schedules
+           for (w, i) in ((16, 16), (8, 16), (16, 8), (8, 8), (4, 16))]
 CONFIGS = [s + (0,) for s in SHAPES + COMPACT] + [(8, 16, 2, 1), (4, 16, 1, 1000), (16, 8, 1, 3),
-                                                  (16, 16, 8, 1000), (8, 16, 8, 1)]
+                                                  (16, 16, 8, 1000), (8, 16, 8, 1), (16, 8, 9, 1000), (16, 8, 9, 1)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
@@ -92,7 +93,7 @@ def test_launch_configs_do_not_change_output(cfg, rounds):
         assert np.array_equal(gpu(x, 9, rounds), oracle.shuffle(x, 9, rounds)), (cfg, n)
 
 
-@pytest.mark.parametrize("cfg", [(16, 16, 8, 0), (8, 8, 8, 0)])
+@pytest.mark.parametrize("cfg", [(16, 16, 8, 0), (8, 8, 8, 0), (16, 8, 9, 0), (8, 16, 9, 0)])
 def test_compact_schedule_element_sizes(cfg):
     assert B.bs_set_config(*cfg) == B.BS_OK
     rng = np.random.default_rng(8)
