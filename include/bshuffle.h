@@ -189,8 +189,8 @@ bs_status bs_shuffle_lcg(const void *in, void *out, uint64_t n, uint32_t elem_by
  * tile's kept images are first compacted in LDS and then gathered and stored
  * by all lanes in rank order; or BS_DEPTH_COMPACT_PIPE, the same with the next
  * tile's cipher computed while the current tile's gathers are in flight.  The
- * compacted schedules serve single shuffles with k <= 32; batched launches run
- * such a shape with depth 1.
+ * compacted schedules serve batched launches and single shuffles with k <= 32
+ * (larger domains always run the register schedule with 64-bit indices).
  * Compiled shapes (waves, items, depth): (4,16,2) (8,16,2) (8,16,1)
  * (16,16,1) (16,8,1) (8,8,2) (4,16,1) (16,16,2) (16,8,2), and with either
  * compacted schedule (16,16) (8,16) (16,8) (8,8) (4,16).  grid_mult: 0 = a persistent grid of

@@ -53,6 +53,17 @@ bs_status bs_probe_shuffle_unfused(const void *in, void *out, uint64_t n, uint32
                                    uint32_t rounds, void *scratch, size_t scratch_bytes, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/*
+ * bs_probe_set_xcd_mode -- how batched launches place segments on the 8 XCDs
+ * (never changes results).  1: the batch's tiles are split into 8 ranges of
+ * whole segments with about equal tile counts; workgroups take tiles from the
+ * range of their own XCD first, so a segment's random reads stay in one L2.
+ * 0: one range, tiles handed out in order to every XCD.  2 (default): ranges
+ * when segments average at least 4 tiles.  BS_EINVAL for other values.
+ * Applies to every later call from every thread.
+ */
+bs_status bs_probe_set_xcd_mode(uint32_t mode);
+
 /* Selects plain (0) or non-temporal (1) output stores for bs_shuffle. */
 bs_status bs_probe_set_store_mode(uint32_t nontemporal);
 

@@ -21,8 +21,7 @@ from . import binding as B
 
 TUNED_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_configs.json")
 SHAPES = [(4, 16, 2), (8, 16, 2), (8, 16, 1), (16, 16, 1), (16, 8, 1), (8, 8, 2), (4, 16, 1), (16, 16, 2), (16, 8, 2)]
-# LDS-compacted schedules (single shuffles only): depth field = B.DEPTH_COMPACT or
-# B.DEPTH_COMPACT_PIPE
+# LDS-compacted schedules: depth field = B.DEPTH_COMPACT or B.DEPTH_COMPACT_PIPE
 COMPACT_SHAPES = [(w, i, d) for d in (B.DEPTH_COMPACT, B.DEPTH_COMPACT_PIPE)
                   for (w, i) in ((16, 16), (8, 16), (16, 8), (8, 8), (4, 16))]
 GRIDS = [0, 1, 2, B.GRID_ONE_PER_TILE]
@@ -66,8 +65,8 @@ def _dtype(torch, eb):
     return {1: torch.uint8, 2: torch.int16, 4: torch.int32, 8: torch.int64}[eb] if eb != 16 else torch.int32
 
 
-def _candidates(kind: int = 0):
-    for sh in SHAPES + (COMPACT_SHAPES if kind == KIND_SINGLE else []):
+def _candidates():
+    for sh in SHAPES + COMPACT_SHAPES:
         for g in GRIDS:
             yield sh + (g,)
 
@@ -85,7 +84,7 @@ def tune_single(torch, bs, elem_bytes: int, size_bits: int, rounds: int, iters: 
     y = torch.empty_like(x)
     xl, yl = x[:lo], y[:lo]
     best = None
-    for cfg in _candidates(KIND_SINGLE):
+    for cfg in _candidates():
         if B.bs_set_config(*cfg) != B.BS_OK:
             continue
         ms = _time(torch, lambda: bs.shuffle(x, 7, rounds, out=y), iters)
@@ -117,7 +116,7 @@ def tune_batched(torch, bs, elem_bytes: int, size_bits: int, rounds: int, iters:
     sd = torch.from_numpy(seeds.view(np.int64)).to(device)
     real_bits = int(np.ceil(np.log2(max(1, -(-total // count)))))
     best = None
-    for cfg in _candidates(KIND_BATCHED):
+    for cfg in _candidates():
         if B.bs_set_config(*cfg) != B.BS_OK:
             continue
         ms = _time(torch, lambda: bs.shuffle_batched(x, off, sd, rounds, out=y), iters)

@@ -61,6 +61,7 @@ _SIGNATURES = {
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
     "bs_probe_set_store_mode": (_i32, [_u32]),
+    "bs_probe_set_xcd_mode": (_i32, [_u32]),
 }
 
 
@@ -141,7 +142,7 @@ def bs_workspace_error(workspace, stream) -> int:
 
 
 GRID_ONE_PER_TILE = 1000
-DEPTH_COMPACT = 8  # tile schedule: kept images compacted through LDS (single shuffles)
+DEPTH_COMPACT = 8  # tile schedule: kept images compacted through LDS
 DEPTH_COMPACT_PIPE = 9  # same, with the next tile's cipher overlapping the current tile's gathers
 
 
@@ -218,6 +219,10 @@ def bs_probe_gather(in_ptr, n_in, out_ptr, idx_ptr, n, elem_bytes, stream) -> in
 
 def bs_probe_cipher_scan(n, seed, rounds, workspace, workspace_bytes, stream) -> int:
     return int(lib().bs_probe_cipher_scan(n, seed & (2**64 - 1), rounds, workspace, workspace_bytes, stream))
+
+
+def bs_probe_set_xcd_mode(mode: int) -> int:
+    return int(lib().bs_probe_set_xcd_mode(mode))
 
 
 def bs_probe_set_store_mode(nontemporal: int) -> int:

@@ -47,6 +47,7 @@ bsd::LaunchConfig pick_config(uint32_t kind, uint32_t elem_bytes, uint32_t bits)
   return it != g_tuned.end() ? it->second : g_cfg;
 }
 bool g_nontemporal_store = false;
+uint32_t g_xcd_mode = 2;  // batched tile ranges per XCD: 0 off, 1 on, 2 automatic
 
 struct CacheEntry {
   void* ptr = nullptr;
@@ -390,6 +391,7 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
   a.capacity = uint32_t(lay.capacity);
   a.tile = 64u * cfg.waves * cfg.items;
   a.nontemporal = g_nontemporal_store ? 1u : 0u;
+  a.xcd_mode = g_xcd_mode;
   a.hdr = reinterpret_cast<bsd::WorkspaceHeader*>(base);
   a.status = reinterpret_cast<uint64_t*>(base + lay.status);
   a.segs = reinterpret_cast<bsd::SegmentInfo*>(base + lay.segs);
@@ -408,6 +410,13 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
 }  // extern "C"
 
 // ------------------------------------------------------- probe entry points --
+extern "C" bs_status bs_probe_set_xcd_mode(uint32_t mode) {
+  if (mode > 2) return BS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_xcd_mode = mode;
+  return BS_OK;
+}
+
 extern "C" bs_status bs_probe_set_store_mode(uint32_t nontemporal) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_nontemporal_store = nontemporal != 0;

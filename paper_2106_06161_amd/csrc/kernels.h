@@ -50,12 +50,16 @@ struct BatchArgs {
   uint32_t capacity;        // status words the workspace holds (= max tiles)
   uint32_t tile;            // indices per tile of the launch configuration
   uint32_t nontemporal;     // 1: output stores bypass cache retention
+  uint32_t xcd_mode;        // tile ranges per XCD: 0 off, 1 on, 2 when segments average
+                            // at least kXcdMinTilesPerSegment tiles
   WorkspaceHeader* hdr;
   uint64_t* status;
   SegmentInfo* segs;        // num_segments records
   uint32_t* keys;           // num_segments * (rounds + 1): masked keys, then 0
   uint32_t* tile_segment;   // capacity entries: segment owning each tile
 };
+
+constexpr uint32_t kXcdMinTilesPerSegment = 4;
 
 struct LaunchConfig {
   uint32_t waves;      // wavefronts per workgroup
@@ -82,9 +86,8 @@ hipError_t launch_tile_prefix(const uint64_t* counts, uint64_t* prefix, uint32_t
 hipError_t launch_cipher_table(const SingleArgs& a, uint32_t* table, hipStream_t stream);
 
 bool config_supported(const LaunchConfig& cfg);
-// Batched launches have no compacted schedule: a compacted shape runs the
-// register schedule with one tile in flight (the default shape if that one is
-// not compiled).  The tile size follows the returned shape.
+// The shape a batched launch runs: cfg when compiled, else the default
+// register shape.  The tile size follows the returned shape.
 LaunchConfig batch_config(const LaunchConfig& cfg);
 
 using SingleFn = void (*)(SingleArgs);

@@ -82,6 +82,8 @@ template <int WAVES>
 struct TileLds {
   uint32_t ticket;
   uint32_t next_ticket;
+  uint32_t cursor;  // XCD tickets: ranges this workgroup has found exhausted
+  uint32_t xcd_first[kXcds + 1];  // XCD tickets: the ranges (fixed for the launch)
   uint32_t gen;
   uint32_t last;
   uint32_t limit;
@@ -89,16 +91,62 @@ struct TileLds {
   uint64_t tile_exclusive;
 };
 
-// Starts a workgroup: reads the launch generation and takes the first ticket.
-// Plain (relaxed) atomics: the header was last written by an earlier kernel,
-// and kernel boundaries already make those writes visible; an acquire here
-// would invalidate the XCD's L2 once per workgroup.
+// Tickets.  Single shuffles hand out tiles from one counter in launch order.
+// Batched launches (XCD = true) may split the batch's tiles into kXcds ranges
+// of whole segments (set up by the batch kernels before the launch); a
+// workgroup takes tiles from the range of its own XCD first and moves on to
+// the next XCD's range only when its own is exhausted, so a segment's tiles,
+// and the random reads inside that segment, mostly stay in one L2.  Every
+// range is handed out in tile order, so a tile still only waits on tiles
+// owned by running workgroups.  Called by one lane at a time; lds.cursor
+// counts the ranges that workgroup found exhausted.  Returns 0xFFFFFFFF when
+// every range is exhausted.
+template <bool XCD, int WAVES>
+__device__ __forceinline__ uint32_t take_ticket(WorkspaceHeader* hdr, TileLds<WAVES>& lds) {
+  if constexpr (!XCD) {
+    return atomicAdd(&hdr->ticket, 1u);
+  } else {
+    const uint32_t home = blockIdx.x % kXcds;
+    while (lds.cursor < kXcds) {
+      const uint32_t x = (home + lds.cursor) % kXcds;
+      const uint32_t begin = lds.xcd_first[x], end = lds.xcd_first[x + 1];
+      if (begin < end) {
+        const uint32_t t = begin + atomicAdd(&hdr->xcd_ticket[x], 1u);
+        if (t < end) return t;
+      }
+      ++lds.cursor;
+    }
+    return 0xFFFFFFFFu;
+  }
+}
+
+// The lane that takes a workgroup's tickets after the first one.  The register
+// schedule takes the next ticket once every wave of the workgroup has counted
+// its keeps (a ticket taken earlier sits unstarted while later tiles of its
+// segment wait on it); the compacted schedule takes it as the tile's
+// compaction starts, which hides the atomic's latency behind the compaction.
 template <int WAVES>
+__device__ __forceinline__ bool ticket_lane() {
+  constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
+  return threadIdx.x == kTicketWave * 64u;
+}
+
+// Starts a workgroup: reads the launch generation (and the XCD ranges) and
+// takes the first ticket.  Plain (relaxed) atomics: the header was last
+// written by an earlier kernel, and kernel boundaries already make those
+// writes visible; an acquire here would invalidate the XCD's L2 once per
+// workgroup.
+template <bool XCD = false, int WAVES>
 __device__ __forceinline__ void group_begin(WorkspaceHeader* hdr, TileLds<WAVES>& lds) {
   if (threadIdx.x == 0) {
     lds.gen = __hip_atomic_load(&hdr->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     lds.limit = __hip_atomic_load(&hdr->batch_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    lds.ticket = atomicAdd(&hdr->ticket, 1u);
+    lds.cursor = 0;
+    if constexpr (XCD) {
+#pragma unroll
+      for (uint32_t x = 0; x <= kXcds; ++x) lds.xcd_first[x] = hdr->xcd_first[x];
+    }
+    lds.ticket = take_ticket<XCD>(hdr, lds);
   }
   __syncthreads();
 }
@@ -127,6 +175,8 @@ __device__ __forceinline__ void group_end(WorkspaceHeader* hdr, uint64_t* status
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
+    if (threadIdx.x < kXcds)
+      __hip_atomic_store(&hdr->xcd_ticket[threadIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) {
       __hip_atomic_store(&hdr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&hdr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -241,8 +291,9 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, MODE, ITEMS, WIDE>& 
 // Returns this wave's output base: kept indices before the tile plus those
 // of lower waves in the tile.  With LOOKBACK the tile's prefix comes from the
 // decoupled look-back; otherwise from tile_prefix[status_idx] (written by an
-// earlier pass).  Takes the workgroup's next ticket.
-template <int WAVES, bool LOOKBACK = true>
+// earlier pass).  Takes the workgroup's next ticket once every wave has
+// counted its keeps.
+template <int WAVES, bool LOOKBACK = true, bool XCD = false>
 __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* status, uint32_t status_first,
                                               uint32_t status_idx, uint32_t tag, WorkspaceHeader* hdr,
                                               TileLds<WAVES>& lds, const uint64_t* tile_prefix = nullptr) {
@@ -257,8 +308,7 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
     wave_exclusive += (uint32_t(w) < wave) ? c : 0u;
     tile_total += c;
   }
-  constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
-  if (wave == kTicketWave && lane == 0) lds.next_ticket = atomicAdd(&hdr->ticket, 1u);
+  if (ticket_lane<WAVES>()) lds.next_ticket = take_ticket<XCD>(hdr, lds);
   if (wave == 0) {
     uint64_t ex;
     if constexpr (LOOKBACK)
@@ -346,7 +396,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
     if (tile < a.num_tiles) {
       tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile,
                                                           a.table, a.lcg_a, a.lcg_c);
-      cur_prefix = tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.tile_prefix);
+      cur_prefix =
+          tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.tile_prefix);
     }
     while (tile < a.num_tiles) {
       const uint32_t next = lds.next_ticket;
@@ -356,7 +407,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
                                                             a.table, a.lcg_a, a.lcg_c);
       tile_store(cur, a.in, a.out, a.n, cur_prefix, nt);
       if (more) {
-        cur_prefix = tile_scan<WAVES, LOOKBACK>(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds, a.tile_prefix);
+        cur_prefix =
+            tile_scan<WAVES, LOOKBACK>(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds, a.tile_prefix);
         cur = nxt;
       }
       tile = next;
@@ -386,22 +438,31 @@ struct CompactLds {
   uint32_t y[64 * WAVES * ITEMS];  // kept images of the tile, in rank order
 };
 
-// Compacts the tile whose images are in c into LDS, issues its gathers, runs
-// its look-back and stores it.  With PIPE, the cipher of the next tile (taken
-// from the ticket counter during the compaction) runs between the gathers and
-// the stores, so its VALU work covers the gathers' latency; c then holds the
-// next tile's images on return.  Returns the next tile.
-template <int EB, bool ODD, int WAVES, int ITEMS, int BIJ, bool PIPE, bool LOOKBACK>
-__device__ __forceinline__ uint32_t compact_tile(uint32_t tile, PendingTile<4, kIndices, ITEMS, false>& c,
-                                                 const SingleArgs& a, uint32_t tag, bool nt,
-                                                 CompactLds<WAVES, ITEMS>& lds) {
+// One tile as the compacted schedule sees it.
+struct CompactView {
+  const uint8_t* in;      // records of the tile's shuffle (segment)
+  uint8_t* out;
+  uint64_t n;             // records in the shuffle (bounds the stores)
+  uint32_t status_first;  // status word of the shuffle's first tile
+  uint32_t status_idx;    // the tile's own status word
+};
+
+// Compacts the tile whose images are in c into LDS, issues its gathers, finds
+// its prefix and stores it.  The next ticket is taken as the call starts and
+// published to the workgroup with the compaction.
+// With PIPE, next_cipher(next) runs between the gathers and the stores so its
+// VALU work covers the gathers' latency; it leaves the next tile's images in
+// c.  Returns the next ticket.
+template <int EB, int WAVES, int ITEMS, bool PIPE, bool LOOKBACK, bool XCD, typename NextCipher>
+__device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTile<4, kIndices, ITEMS, false>& c,
+                                                 WorkspaceHeader* hdr, uint64_t* status,
+                                                 const uint64_t* tile_prefix, uint32_t tag, bool nt,
+                                                 CompactLds<WAVES, ITEMS>& lds, NextCipher&& next_cipher) {
   using T = typename Payload<EB>::T;
   constexpr uint32_t kThreads = 64u * WAVES;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if constexpr (!PIPE)
-    tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile,
-                                                           a.table, a.lcg_a, a.lcg_c);
+  const uint32_t tk = ticket_lane<WAVES>() ? take_ticket<XCD>(hdr, lds.t) : 0u;
   if (lane == 0) lds.t.wave_count[wave] = c.wave_count;
   __syncthreads();
   uint32_t pos = 0, total = 0;
@@ -419,8 +480,7 @@ __device__ __forceinline__ uint32_t compact_tile(uint32_t tile, PendingTile<4, k
     if (keep) lds.y[pos + below] = c.val[j];
     pos += uint32_t(__builtin_popcountll(m));
   }
-  constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
-  if (wave == kTicketWave && lane == 0) lds.t.next_ticket = atomicAdd(&a.hdr->ticket, 1u);
+  if (ticket_lane<WAVES>()) lds.t.next_ticket = tk;
   __syncthreads();
   const uint32_t next = lds.t.next_ticket;
   // gathers for ranks threadIdx.x + q * kThreads, issued before the look-back;
@@ -432,22 +492,18 @@ __device__ __forceinline__ uint32_t compact_tile(uint32_t tile, PendingTile<4, k
   for (int q = 0; q < ITEMS; ++q) {
     if (uint32_t(q) < steps) {
       const uint32_t p = min(threadIdx.x + uint32_t(q) * kThreads, total - 1);
-      v[q] = load_record<EB>(a.in, lds.y[p]);
+      v[q] = load_record<EB>(t.in, lds.y[p]);
     }
   }
   if (wave == 0) {
     uint64_t ex;
     if constexpr (LOOKBACK)
-      ex = lookback_exclusive_prefix(a.status, 0u, tile, tag, uint64_t(total), &a.hdr->error);
+      ex = lookback_exclusive_prefix(status, t.status_first, t.status_idx, tag, uint64_t(total), &hdr->error);
     else
-      ex = a.tile_prefix[tile];  // written by an earlier scan pass
+      ex = tile_prefix[t.status_idx];  // written by an earlier scan pass
     if (lane == 0) lds.t.tile_exclusive = ex;
   }
-  if constexpr (PIPE) {
-    if (next < a.num_tiles)
-      tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, next,
-                                                             a.table, a.lcg_a, a.lcg_c);
-  }
+  if constexpr (PIPE) next_cipher(next);
   __syncthreads();
   const uint64_t prefix = lds.t.tile_exclusive;
 #pragma unroll
@@ -455,11 +511,11 @@ __device__ __forceinline__ uint32_t compact_tile(uint32_t tile, PendingTile<4, k
     const uint32_t p = threadIdx.x + uint32_t(q) * kThreads;
     // ranks are < n by construction; the bound only keeps a timed-out
     // look-back from writing outside the buffer
-    if (uint32_t(q) < steps && p < total && prefix + p < a.n) {
+    if (uint32_t(q) < steps && p < total && prefix + p < t.n) {
       if (nt)
-        store_record<EB, true>(a.out, prefix + p, v[q]);
+        store_record<EB, true>(t.out, prefix + p, v[q]);
       else
-        store_record<EB, false>(a.out, prefix + p, v[q]);
+        store_record<EB, false>(t.out, prefix + p, v[q]);
     }
   }
   return next;
@@ -482,12 +538,19 @@ __global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shu
   const bool nt = a.nontemporal != 0;
   uint32_t tile = lds.t.ticket;
   PendingTile<4, kIndices, ITEMS, false> c;
-  if constexpr (PIPE) {
-    if (tile < a.num_tiles)
-      tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, tile,
-                                                             a.table, a.lcg_a, a.lcg_c);
+  auto cipher = [&](uint32_t t) {
+    tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, t,
+                                                           a.table, a.lcg_a, a.lcg_c);
+  };
+  if (PIPE && tile < a.num_tiles) cipher(tile);
+  while (tile < a.num_tiles) {
+    if (!PIPE) cipher(tile);
+    const CompactView v{a.in, a.out, a.n, 0u, tile};
+    tile = compact_core<EB, WAVES, ITEMS, PIPE, LOOKBACK, false>(v, c, a.hdr, a.status, a.tile_prefix, tag, nt, lds,
+                                                          [&](uint32_t nx) {
+                                                            if (nx < a.num_tiles) cipher(nx);
+                                                          });
   }
-  while (tile < a.num_tiles) tile = compact_tile<EB, ODD, WAVES, ITEMS, BIJ, PIPE, LOOKBACK>(tile, c, a, tag, nt, lds);
   group_end(a.hdr, a.status, a.capacity, gen, lds.t);
 }
 
@@ -575,7 +638,7 @@ template <int EB, int WAVES, int ITEMS, int DEPTH>
 __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) void shuffle_batched_kernel(
     const BatchArgs a) {
   __shared__ TileLds<WAVES> lds;
-  group_begin(a.hdr, lds);
+  group_begin<true>(a.hdr, lds);
   const uint32_t gen = lds.gen;
   const uint32_t tag = gen & kTagMask;
   const uint32_t limit = lds.limit;
@@ -586,7 +649,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
     while (tile < limit) {
       const BatchTile b = batch_tile<EB>(a, tile);
       batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
-      const uint64_t prefix = tile_scan(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
+      const uint64_t prefix =
+          tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
       tile_store(cur, nullptr, b.out, b.n, prefix, nt);
       tile = lds.next_ticket;
     }
@@ -598,7 +662,7 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
     if (tile < limit) {
       const BatchTile b = batch_tile<EB>(a, tile);
       batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
-      cur_prefix = tile_scan(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
+      cur_prefix = tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
       cur_out = b.out;
       cur_n = b.n;
     }
@@ -612,7 +676,7 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
       }
       tile_store(cur, nullptr, cur_out, cur_n, cur_prefix, nt);
       if (more) {
-        cur_prefix = tile_scan(nxt.wave_count, a.status, b.first_tile, next, tag, a.hdr, lds);
+        cur_prefix = tile_scan<WAVES, true, true>(nxt.wave_count, a.status, b.first_tile, next, tag, a.hdr, lds);
         cur = nxt;
         cur_out = b.out;
         cur_n = b.n;
@@ -621,6 +685,57 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
     }
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds);
+}
+
+// Batched form of the compacted schedule: a tile's segment (slice, domain,
+// keys, first status word) is looked up per tile; with PIPE the next tile's
+// segment and cipher are taken while the current tile's gathers are in flight.
+// (The pipelined batched form keeps the next tile's segment record live as
+// well; it does not fit in 64 VGPRs, so it is sized for one workgroup per CU.)
+template <int EB, int ITEMS, bool PIPE>
+constexpr int kBatchCompactMinWaves = PIPE ? 1 : kCompactMinWaves<EB, ITEMS>;
+
+template <int EB, int WAVES, int ITEMS, bool PIPE>
+__global__ __launch_bounds__(WAVES * 64, (kBatchCompactMinWaves<EB, ITEMS, PIPE>)) void shuffle_batched_compact_kernel(
+    const BatchArgs a) {
+  __shared__ CompactLds<WAVES, ITEMS> lds;
+  group_begin<true>(a.hdr, lds.t);
+  const uint32_t gen = lds.t.gen;
+  const uint32_t tag = gen & kTagMask;
+  const uint32_t limit = lds.t.limit;
+  const bool nt = a.nontemporal != 0;
+  uint32_t tile = lds.t.ticket;
+  PendingTile<4, kIndices, ITEMS, false> c;
+  auto cipher = [&](const BatchTile& b) {
+    if (b.odd)
+      tile_gather<4, kIndices, true, WAVES, ITEMS, false>(c, nullptr, b.n, b.domain, b.cs, a.rounds, b.keys,
+                                                          b.tile_in_segment);
+    else
+      tile_gather<4, kIndices, false, WAVES, ITEMS, false>(c, nullptr, b.n, b.domain, b.cs, a.rounds, b.keys,
+                                                           b.tile_in_segment);
+  };
+  BatchTile b;
+  if (PIPE && tile < limit) {
+    b = batch_tile<EB>(a, tile);
+    cipher(b);
+  }
+  while (tile < limit) {
+    if (!PIPE) {
+      b = batch_tile<EB>(a, tile);
+      cipher(b);
+    }
+    const CompactView v{b.in, b.out, b.n, b.first_tile, tile};
+    BatchTile nb;
+    tile = compact_core<EB, WAVES, ITEMS, PIPE, true, true>(v, c, a.hdr, a.status, nullptr, tag, nt, lds,
+                                                      [&](uint32_t nx) {
+                                                        if (nx < limit) {
+                                                          nb = batch_tile<EB>(a, nx);
+                                                          cipher(nb);
+                                                        }
+                                                      });
+    if (PIPE) b = nb;
+  }
+  group_end(a.hdr, a.status, a.capacity, gen, lds.t);
 }
 
 // Variants outside the main shape table use one fixed shape.
@@ -684,6 +799,15 @@ SingleFn pick_single_eb(bool odd, bool wide, const LaunchConfig& c) {
 
 template <int EB>
 BatchFn pick_batch_eb(const LaunchConfig& c) {
+  if (c.depth == kDepthCompact || c.depth == kDepthCompactPipe) {
+    const bool pipe = c.depth == kDepthCompactPipe;
+#define BSD_PICK(W, I)              \
+  if (c.waves == W && c.items == I) \
+    return pipe ? &shuffle_batched_compact_kernel<EB, W, I, true> : &shuffle_batched_compact_kernel<EB, W, I, false>;
+    BSD_FOR_EACH_COMPACT_SHAPE(BSD_PICK)
+#undef BSD_PICK
+    return nullptr;
+  }
 #define BSD_PICK(W, I, D) \
   if (c.waves == W && c.items == I && c.depth == D) return &shuffle_batched_kernel<EB, W, I, D>;
   BSD_FOR_EACH_SHAPE(BSD_PICK)

@@ -76,6 +76,11 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(const Batch
   if (tid == 0) {
     const uint32_t total = bad ? 0u : carry;
     if (bad) atomicOr(&a.hdr->error, kErrBadBatch);
+    // XCD ranges start as one range (every tile on XCD 0's counter, which all
+    // workgroups reach); with ranges on, batch_fill_kernel moves each boundary
+    // down to the first segment that starts at or after x/8 of the tiles
+    a.hdr->xcd_first[0] = 0;
+    for (uint32_t x = 1; x <= kXcds; ++x) a.hdr->xcd_first[x] = total;
     __hip_atomic_store(&a.hdr->batch_tiles, total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -87,8 +92,18 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(const BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t total = __hip_atomic_load(&a.hdr->batch_tiles, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
   if (total == 0) return;
+  const bool ranges = a.xcd_mode == 1 ||
+                      (a.xcd_mode == 2 && uint64_t(total) >= uint64_t(kXcdMinTilesPerSegment) * a.num_segments);
   for (uint32_t s = wave_global; s < a.num_segments; s += waves_total) {
     const SegmentInfo si = a.segs[s];
+    // XCD ranges of whole segments with about total/kXcds tiles each: the
+    // boundary of range x is the first segment start at or after x*total/kXcds
+    // (segments without tiles share the next segment's start)
+    if (ranges && lane > 0 && lane < kXcds) {
+      const uint32_t p = uint32_t((uint64_t(lane) * total + kXcds - 1) / kXcds);
+      const uint32_t prev = (s == 0) ? 0u : a.segs[s - 1].first_tile;
+      if (si.first_tile >= p && (s == 0 || prev < p)) atomicMin(&a.hdr->xcd_first[lane], si.first_tile);
+    }
     if (si.n == 0) continue;
     const uint64_t dom = uint64_t(1) << si.k;
     const uint32_t tiles = uint32_t((dom + a.tile - 1) / a.tile);
@@ -167,10 +182,7 @@ hipError_t launch_single(const SingleArgs& a0, uint32_t eb, bool nt, const Launc
 }
 
 LaunchConfig batch_config(const LaunchConfig& c) {
-  LaunchConfig b = c;
-  if (b.depth == kDepthCompact || b.depth == kDepthCompactPipe) b.depth = 1;
-  if (!config_supported(b)) b = {16, 16, 1, c.grid_mult};
-  return b;
+  return config_supported(c) ? c : LaunchConfig{16, 16, 1, c.grid_mult};
 }
 
 hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& cfg, uint32_t num_cus,

@@ -37,15 +37,21 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // ~seconds of polling before giving 
 constexpr uint32_t kErrTimeout = 1u;
 constexpr uint32_t kErrBadBatch = 2u;
 
+// XCDs (accelerator complex dies, one L2 each) of the device.  Workgroups are
+// dispatched to them round-robin, so workgroup b runs on XCD b % kXcds.
+constexpr uint32_t kXcds = 8;
+
 // First 256 bytes of every workspace.
 struct WorkspaceHeader {
-  uint32_t ticket;         // next tile handed out in this launch
+  uint32_t ticket;         // next tile handed out in this launch (single shuffles)
   uint32_t done;           // workgroups finished in this launch
   uint32_t gen;            // launch generation; its low 24 bits tag status words
   uint32_t error;          // sticky error bits
   uint32_t capacity;       // status words the workspace holds (set at init)
   uint32_t batch_tiles;    // batched launches: tiles of the current batch
-  uint32_t pad[58];
+  uint32_t xcd_ticket[kXcds];     // batched launches: next tile of each XCD's range
+  uint32_t xcd_first[kXcds + 1];  // batched launches: XCD x owns tiles [xcd_first[x], xcd_first[x+1])
+  uint32_t pad[41];
 };
 static_assert(sizeof(WorkspaceHeader) == 256, "header is 256 bytes");
 

@@ -103,16 +103,16 @@ def test_config_round_trip():
     assert B.bs_get_config() == before
 
 
-def test_compact_shape_maps_to_register_schedule_for_batches():
-    """A forced compacted shape applies to single shuffles; batched launches
-    report (and run) the register schedule with the same tile."""
+def test_forced_shape_applies_to_both_call_kinds():
+    """A forced shape applies to single and batched launches, except that
+    domains above 2^32 always run the 64-bit index shape."""
     try:
         assert B.bs_set_config(16, 8, B.DEPTH_COMPACT, 0) == B.BS_OK
         assert B.bs_query_config(0, 4, 1 << 20) == (16, 8, B.DEPTH_COMPACT, 0)
-        assert B.bs_query_config(1, 4, 1 << 20, 16) == (16, 8, 1, 0)
-        assert B.bs_set_config(8, 8, B.DEPTH_COMPACT, 0) == B.BS_OK
-        assert B.bs_query_config(1, 4, 1 << 20, 16) == (16, 16, 1, 0)  # (8, 8, 1) is not compiled
-        assert B.bs_query_config(0, 4, (1 << 32) + 1) == (8, 16, 1, 0)  # 64-bit index path
+        assert B.bs_query_config(1, 4, 1 << 20, 16) == (16, 8, B.DEPTH_COMPACT, 0)
+        assert B.bs_set_config(8, 8, B.DEPTH_COMPACT_PIPE, 1) == B.BS_OK
+        assert B.bs_query_config(1, 4, 1 << 20, 16) == (8, 8, B.DEPTH_COMPACT_PIPE, 1)
+        assert B.bs_query_config(0, 4, (1 << 32) + 1) == (8, 16, 1, 1)  # 64-bit index path
     finally:
         B.bs_set_config(0, 0, 0, 0)
 
@@ -142,9 +142,7 @@ def test_shipped_tuned_table_is_valid():
 
     entries = autotune.load()
     for e in entries:
-        shapes = [tuple(s) for s in autotune.SHAPES]
-        if e["kind"] == autotune.KIND_SINGLE:
-            shapes += [tuple(s) for s in autotune.COMPACT_SHAPES]
+        shapes = [tuple(s) for s in autotune.SHAPES + autotune.COMPACT_SHAPES]
         assert (e["waves"], e["items"], e["depth"]) in shapes
     assert autotune.apply(entries) == len(entries)
 
@@ -175,3 +173,9 @@ def test_lcg_argument_checks():
     assert B.bs_shuffle_lcg(None, FAKE_OUT, 10, 4, 1, None, 0, None) == B.BS_EINVAL
     assert B.bs_shuffle_lcg(None, None, 0, 4, 1, None, 0, None) == B.BS_OK
     assert B.bs_shuffle_lcg(FAKE_IN, FAKE_OUT, B.MAX_ITEMS + 1, 1, 1, None, 0, None) == B.BS_EINVAL
+
+
+def test_xcd_mode_argument_check():
+    assert B.bs_probe_set_xcd_mode(3) == B.BS_EINVAL
+    for m in (0, 1, 2):
+        assert B.bs_probe_set_xcd_mode(m) == B.BS_OK

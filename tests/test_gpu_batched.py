@@ -19,8 +19,10 @@ DEV = "cuda:0"
 @pytest.fixture(autouse=True)
 def _default_config():
     B.bs_set_config(0, 0, 0, 0)
+    B.bs_probe_set_xcd_mode(2)
     yield
     B.bs_set_config(0, 0, 0, 0)
+    B.bs_probe_set_xcd_mode(2)
     assert bs.workspace_error() == B.BS_OK
 
 
@@ -67,8 +69,10 @@ def test_batched_equals_single_calls():
         assert np.array_equal(single.cpu().numpy(), got[lo:hi]), s
 
 
+@pytest.mark.parametrize("cfg", [(0, 0, 0, 0), (16, 16, 9, 0), (16, 8, 8, 0)])
 @pytest.mark.parametrize("dtype,width", [(np.uint8, 0), (np.uint16, 0), (np.uint64, 0), (np.float32, 4)])
-def test_batched_element_sizes(dtype, width):
+def test_batched_element_sizes(dtype, width, cfg):
+    assert B.bs_set_config(*cfg) == B.BS_OK
     b = W.batch(40, 50, 50_000, seed=11)
     n = b["total"]
     rng = np.random.default_rng(2)
@@ -79,9 +83,16 @@ def test_batched_element_sizes(dtype, width):
     assert np.array_equal(got, oracle.shuffle_batched(x, b["offsets"], b["seeds"], 24))
 
 
-@pytest.mark.parametrize("cfg", [(16, 16, 1, 0), (4, 16, 2, 0), (8, 8, 2, 3), (16, 8, 1, 1000), (8, 16, 1, 1)])
-def test_batched_configs_do_not_change_output(cfg):
+COMPACT = [(w, i, d, 0) for d in (B.DEPTH_COMPACT, B.DEPTH_COMPACT_PIPE)
+           for (w, i) in ((16, 16), (8, 16), (16, 8), (8, 8), (4, 16))]
+
+
+@pytest.mark.parametrize("cfg", [(16, 16, 1, 0), (4, 16, 2, 0), (8, 8, 2, 3), (16, 8, 1, 1000), (8, 16, 1, 1)] +
+                         COMPACT + [(16, 16, 9, 1000), (16, 8, 8, 2)])
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_batched_configs_do_not_change_output(cfg, xcd):
     assert B.bs_set_config(*cfg) == B.BS_OK
+    assert B.bs_probe_set_xcd_mode(xcd) == B.BS_OK
     b = W.batch(100, 100, 200_000, seed=4)
     x = W.arange_u32(b["total"])
     got = run_batched(x, b["offsets"], b["seeds"], 24)
@@ -160,3 +171,37 @@ def test_bootstrap_shaped_batch_sampled():
         lo, hi = int(b["offsets"][s]), int(b["offsets"][s + 1])
         want = oracle.shuffle(np.arange(lo, hi, dtype=np.uint32), int(b["seeds"][s]), 24)
         assert np.array_equal(y_np[lo:hi], want), s
+
+
+def test_xcd_ranges_cover_whole_segments():
+    """The batch's tiles are split into 8 XCD ranges made of whole segments,
+    about equal in size; read back from the workspace header after a launch."""
+    assert B.bs_probe_set_xcd_mode(1) == B.BS_OK  # ranges on (auto keeps one range below 4 tiles a segment)
+    b = W.batch(300, 100, 100_000, seed=9)
+    S, total = len(b["sizes"]), b["total"]
+    x = torch.from_numpy(W.arange_u32(total)).to(DEV)
+    off = torch.from_numpy(b["offsets"]).to(DEV)
+    sd = torch.from_numpy(b["seeds"].view(np.int64)).to(DEV)
+    ws = bs.make_workspace(bs.workspace_bytes(total, S), device=DEV)
+    y = bs.shuffle_batched(x, off, sd, 24, workspace=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), oracle.shuffle_batched(W.arange_u32(total), b["offsets"], b["seeds"], 24))
+    hdr = ws[:256].cpu().numpy().view(np.uint32)
+    batch_tiles, xcd_first = int(hdr[5]), hdr[14:23].astype(np.int64)
+    waves, items, _, _ = B.bs_query_config(1, 4, total, S)
+    tile = 64 * waves * items
+    tiles = [0 if n == 0 else -(-(1 << B.bs_domain_bits(int(n))) // tile) for n in b["sizes"]]
+    starts = np.concatenate([[0], np.cumsum(tiles)])
+    assert batch_tiles == starts[-1]
+    assert xcd_first[0] == 0 and xcd_first[8] == batch_tiles
+    assert np.all(np.diff(xcd_first) >= 0)
+    assert set(xcd_first.tolist()) <= set(starts.tolist())  # whole segments per range
+    assert np.diff(xcd_first).max() <= -(-batch_tiles // 8) + max(tiles)
+    # with ranges off, every tile is in the first range
+    assert B.bs_probe_set_xcd_mode(0) == B.BS_OK
+    y = bs.shuffle_batched(x, off, sd, 24, workspace=ws)
+    torch.cuda.synchronize()
+    hdr = ws[:256].cpu().numpy().view(np.uint32)
+    assert hdr[14] == 0 and np.all(hdr[15:23] == batch_tiles)
+    assert np.array_equal(y.cpu().numpy(), oracle.shuffle_batched(W.arange_u32(total), b["offsets"], b["seeds"], 24))
+    assert bs.workspace_error(ws) == B.BS_OK
