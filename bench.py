@@ -21,6 +21,8 @@ Prints ONE JSON line:
                (Bijective0: cipher table, compaction, gather as three passes;
                Bijective1: a separate tile-count and scan pass before the
                gather) and the LCG bijection in the same fused kernel
+  small        n = 100,000 uint32, 4 rounds: per-call latency
+  large        n = 10^9 uint32 and 2.5e8 records of 16 bytes, 24 rounds
   batched      4,096 independent shuffles in one launch vs 4,096 calls
   serving      the continuous-batching server: capacity, p50 / p99 latency
 
@@ -85,6 +87,9 @@ def parse_args():
     p.add_argument("--no-fusion", action="store_true")
     p.add_argument("--fusion-sweep", action="store_true",
                    help="also time every fusion form over n = 2^20 .. 2^29 (+1)")
+    p.add_argument("--no-large", action="store_true")
+    p.add_argument("--sweep", action="store_true",
+                   help="also time the fused kernel and the gather probe over n = 2^w, 2^w+1 (w = 8..30), u32 and u64")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serve-requests", type=int, default=2000)
@@ -273,6 +278,70 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None,
     return res
 
 
+def bench_small(torch, bs, dev, timer) -> dict:
+    """The small single-shuffle workload: n = 100,000 uint32 arange, seed 42,
+    4 rounds (domain 2^17): launch-bound; per-call time on one stream."""
+    n = 100_000
+    x = torch.arange(n, dtype=torch.int32, device=dev)
+    y = torch.empty_like(x)
+    ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+    t = timer.run(lambda: bs.shuffle(x, 42, 4, out=y, workspace=ws), 200, warm=10)
+    return {"workload": "n=100,000 uint32 arange, seed 42, 4 rounds, domain 2^17", "us_per_call": t * 1e6,
+            "Gelem_s": n / t / 1e9}
+
+
+def bench_large(torch, bs, dev, timer, rounds) -> dict:
+    """n = 10^9 uint32 arange (seed 1, domain 2^30) and 2.5e8 records of four
+    float32 (seeded device normal values, seed 11, domain 2^28)."""
+    res = {}
+    n = 10**9
+    x = torch.arange(n, dtype=torch.int32, device=dev)
+    y = torch.empty_like(x)
+    ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+    t = timer.run(lambda: bs.shuffle(x, 1, rounds, out=y, workspace=ws), 3)
+    res["u32_1e9_ms"] = t * 1e3
+    res["u32_1e9_Gelem_s"] = n / t / 1e9
+    res["u32_1e9_alg_GBps"] = 8.0 * n / t / 1e9
+    del x, y
+    n = 250_000_000
+    gen = torch.Generator(device=dev).manual_seed(11)
+    x = torch.randn((n, 4), dtype=torch.float32, device=dev, generator=gen)
+    y = torch.empty_like(x)
+    t = timer.run(lambda: bs.shuffle(x, 11, rounds, out=y, workspace=ws), 3)
+    res["rec16_2p5e8_ms"] = t * 1e3
+    res["rec16_2p5e8_Gelem_s"] = n / t / 1e9
+    res["rec16_2p5e8_alg_GBps"] = 32.0 * n / t / 1e9
+    del x, y
+    if bs.workspace_error(ws) != 0:
+        raise RuntimeError("device-side error in the large workloads")
+    return res
+
+
+def bench_sweep(torch, bs, B, dev, stream, timer, rounds) -> list:
+    """The fused kernel and a random gather with an index array over
+    n = 2^w and 2^w + 1, w = 8..30, for 4- and 8-byte records."""
+    out = []
+    sp = stream.cuda_stream
+    for eb, dt in ((4, torch.int32), (8, torch.int64)):
+        for w in range(8, 31):
+            for n in (1 << w, (1 << w) + 1):
+                if n * eb * 3 > 24 << 30:
+                    continue
+                log(f"bench: sweep elem_bytes={eb} n={n}")
+                x = torch.arange(n, dtype=torch.int64, device=dev).to(dt)
+                y = torch.empty_like(x)
+                ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+                t = timer.run(lambda: bs.shuffle(x, SEED, rounds, out=y, workspace=ws), 5)
+                idx = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
+                tg = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), n, y.data_ptr(), idx.data_ptr(), n, eb, sp), 5)
+                out.append({"elem_bytes": eb, "n": n, "shuffle_ms": t * 1e3, "gather_ms": tg * 1e3,
+                            "Gelem_s": n / t / 1e9, "launch": list(B.bs_query_config(0, eb, n))})
+                if bs.workspace_error(ws) != 0:
+                    raise RuntimeError("device-side error in the sweep")
+                del x, y, idx, ws
+    return out
+
+
 def bench_serving(rounds: int, count: int) -> dict:
     """The continuous-batching server: closed-loop capacity (every request
     arrives at once), then Poisson arrivals at 0.8x that rate."""
@@ -349,7 +418,8 @@ def main() -> int:
         ev1[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_s = sum(a.elapsed_time(b) for a, b in zip(ev0, ev1)) / args.steps * 1e-3
+    per_step = sorted(a.elapsed_time(b) for a, b in zip(ev0, ev1))
+    kernel_s = sum(per_step) / args.steps * 1e-3
     err = bs.workspace_error(ws)
     if err != 0:
         log(f"bench: device-side error {B.status_string(err)}")
@@ -390,10 +460,17 @@ def main() -> int:
             "traffic": traffic["hbm_bytes_per_launch"] if traffic else None,
             "kernel": kernel_label(launch),
             "kernel_ms": kernel_s * 1e3,
+            "kernel_ms_median": per_step[len(per_step) // 2],
+            "kernel_ms_min": per_step[0],
             "algorithmic_bytes_per_launch": alg_bytes,
             "kernel_source_digest": digest,
         },
     }
+    if traffic:
+        result["roofline"]["physical_GBps"] = traffic["hbm_bytes_per_launch"] / kernel_s / 1e9
+        result["roofline"]["fetch_bytes_per_elem"] = traffic["fetch_bytes_per_launch"] / N_HEADLINE
+        result["roofline"]["write_bytes_per_elem"] = traffic["write_bytes_per_launch"] / N_HEADLINE
+        result["roofline"]["traffic_kernel_ms_rocprof"] = traffic["kernel_avg_ms_rocprof"]
     if args.profile:
         print(json.dumps(result), flush=True)
         return 0
@@ -436,6 +513,13 @@ def main() -> int:
                     log(f"bench: fusion sweep n={n}")
                     sweep.append(bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n))
             result["fusion_sweep"] = sweep
+
+    if not args.no_large:
+        log("bench: small (n=100,000, 4 rounds) and large (10^9 uint32; 2.5e8 x 16-byte records) workloads")
+        result["small"] = bench_small(torch, bs, dev, timer)
+        result["large"] = bench_large(torch, bs, dev, timer, rounds)
+    if args.sweep:
+        result["sweep"] = bench_sweep(torch, bs, B, dev, stream, timer, rounds)
 
     if not args.no_batched:
         log("bench: batched vs per-call (4,096 segments, log-uniform sizes in [100, 10^6], PCG64 seed 3)")

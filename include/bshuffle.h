@@ -209,15 +209,45 @@ bs_status bs_get_config(uint32_t *waves_per_group, uint32_t *items_per_lane, uin
                         uint32_t *grid_mult);
 
 /*
- * Tuned launch shapes (filled by the project's autotuner; never change results).
+ * Tuned launch shapes (filled by bs_autotune or a table file; never change results).
  * kind 0 = bs_shuffle, keyed by the domain bits k of the call; kind 1 =
- * bs_shuffle_batched, keyed by ceil(log2(mean segment size)).  A call uses the
- * entry for (kind, elem_bytes, size class) when there is one and no shape was
- * forced with bs_set_config; otherwise the default shape.
+ * bs_shuffle_batched, keyed by ceil(log2(mean segment size)).  Unless a shape
+ * was forced with bs_set_config, a call uses the entry for (kind, elem_bytes,
+ * size class), else the nearest tuned class of that kind and element size
+ * (the largest below, then the smallest above), else the default shape.
  */
 bs_status bs_set_tuned_config(uint32_t kind, uint32_t elem_bytes, uint32_t size_bits, uint32_t waves_per_group,
                               uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
 bs_status bs_clear_tuned_configs(void);
+
+/*
+ * Native autotuner and tuned-table files (text; see the format below).
+ *
+ * bs_autotune -- if cache_path names a table made for the architecture of
+ * `device`, loads it; otherwise times every compiled shape and grid choice on
+ * `device` for element sizes 4, 8 and 16 (single shuffles with domains of
+ * 2^12 .. 2^max_size_bits indices, batched launches with mean segment sizes
+ * of 2^8 .. 2^min(20, max_size_bits)), installs the fastest per size class
+ * and, when cache_path is not NULL, writes the table there.  max_size_bits 0
+ * means 30.  Tuning allocates its own buffers (at most half the free device
+ * memory, 40 GiB at most) and a stream, takes minutes at the default sizes,
+ * and restores any shape forced with bs_set_config.  BS_ENODEV without a
+ * device, BS_EINVAL for a bad device index or an unwritable cache_path.
+ *
+ * bs_load_tuned_configs -- replaces the tuned table with the file's entries
+ * (the arch line is not checked).  BS_EINVAL if the file cannot be read or an
+ * entry is malformed or names a shape that is not compiled; the table is then
+ * unchanged.
+ *
+ * bs_save_tuned_configs -- writes the current tuned table, with the current
+ * device's architecture when one is available.
+ *
+ * Format: '#' starts a comment; "arch <name>" and "rounds <r>" lines; one
+ * entry per line: kind elem_bytes size_bits waves items depth grid_mult [ms].
+ */
+bs_status bs_autotune(int device, const char *cache_path, uint32_t max_size_bits);
+bs_status bs_load_tuned_configs(const char *path);
+bs_status bs_save_tuned_configs(const char *path);
 
 /* The launch shape a call would use: kind 0 = bs_shuffle of `items` records,
  * kind 1 = bs_shuffle_batched of `items` records in num_segments segments. */

@@ -16,6 +16,7 @@ import re
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_PKG)
 LIB_PATH = os.path.join(_PKG, "libbshuffle.so")
+TUNED_FILE = os.path.join(_PKG, "tuned_configs.txt")  # shipped table (bs_autotune format)
 HEADERS = [os.path.join(_ROOT, "include", h) for h in ("bshuffle.h", "bshuffle_probe.h")]
 
 BS_OK, BS_EINVAL, BS_EALIAS, BS_EELEM, BS_ENOMEM, BS_EHIP, BS_ETIMEOUT, BS_ENODEV, BS_EDEVICE = range(9)
@@ -54,6 +55,9 @@ _SIGNATURES = {
     "bs_unshuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_lcg_params": (_i32, [_u64, _u64, _vp, _vp]),
     "bs_shuffle_lcg": (_i32, [_vp, _vp, _u64, _u32, _u64, _vp, _sz, _vp]),
+    "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32]),
+    "bs_load_tuned_configs": (_i32, [ctypes.c_char_p]),
+    "bs_save_tuned_configs": (_i32, [ctypes.c_char_p]),
     "bs_probe_shuffle_two_pass": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_probe_unfused_scratch_bytes": (_sz, [_u64]),
     "bs_probe_shuffle_unfused": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp, _sz, _vp]),
@@ -81,9 +85,8 @@ def lib() -> ctypes.CDLL:
             fn.argtypes = args
         _lib = l
         # launch shapes picked by the autotuner (speed only; results never depend on them)
-        from . import autotune
-
-        autotune.apply(autotune.load())
+        if os.path.exists(TUNED_FILE):
+            l.bs_load_tuned_configs(TUNED_FILE.encode())
     return _lib
 
 
@@ -180,6 +183,18 @@ def bs_permutation(out_ptr, n, index_bytes, seed, rounds, workspace, workspace_b
 def bs_unshuffle(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, workspace_bytes, stream) -> int:
     return int(lib().bs_unshuffle(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, workspace,
                                   workspace_bytes, stream))
+
+
+def bs_autotune(device: int, cache_path: str | None, max_size_bits: int = 0) -> int:
+    return int(lib().bs_autotune(device, cache_path.encode() if cache_path else None, max_size_bits))
+
+
+def bs_load_tuned_configs(path: str) -> int:
+    return int(lib().bs_load_tuned_configs(path.encode()))
+
+
+def bs_save_tuned_configs(path: str) -> int:
+    return int(lib().bs_save_tuned_configs(path.encode()))
 
 
 def bs_lcg_params(n: int, seed: int) -> tuple[int, int]:

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -12,6 +13,7 @@
 
 #include "bshuffle.h"
 #include "bshuffle_probe.h"
+#include "config_state.h"
 #include "kernels.h"
 
 static_assert(BS_GRID_ONE_PER_TILE == bsd::kGridOnePerTile, "grid constant of the ABI");
@@ -41,10 +43,19 @@ bool g_forced = false;  // bs_set_config with a shape: ignore the tuned table
 // segment size.
 std::map<std::tuple<uint32_t, uint32_t, uint32_t>, bsd::LaunchConfig> g_tuned;
 
+// The tuned entry of the size class, else of the nearest tuned class of the
+// same call kind and element size (the largest below, then the smallest
+// above), else the default shape.
 bsd::LaunchConfig pick_config(uint32_t kind, uint32_t elem_bytes, uint32_t bits) {
   if (g_forced) return g_cfg;
-  auto it = g_tuned.find(std::make_tuple(kind, elem_bytes, bits));
-  return it != g_tuned.end() ? it->second : g_cfg;
+  auto it = g_tuned.upper_bound(std::make_tuple(kind, elem_bytes, bits));
+  if (it != g_tuned.begin()) {
+    auto below = std::prev(it);
+    if (std::get<0>(below->first) == kind && std::get<1>(below->first) == elem_bytes) return below->second;
+  }
+  if (it != g_tuned.end() && std::get<0>(it->first) == kind && std::get<1>(it->first) == elem_bytes)
+    return it->second;
+  return g_cfg;
 }
 bool g_nontemporal_store = false;
 uint32_t g_xcd_mode = 2;  // batched tile ranges per XCD: 0 off, 1 on, 2 automatic
@@ -181,6 +192,29 @@ bool ranges_overlap(const void* a, const void* b, uint64_t bytes) {
 }
 
 }  // namespace
+
+namespace bsd {
+
+ConfigState config_state() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return {g_forced, g_cfg};
+}
+
+void restore_config_state(const ConfigState& st) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_forced = st.forced;
+  g_cfg = st.forced ? st.cfg : g_default_cfg;
+}
+
+std::vector<TunedEntry> tuned_snapshot() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  std::vector<TunedEntry> v;
+  for (const auto& kv : g_tuned)
+    v.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second});
+  return v;
+}
+
+}  // namespace bsd
 
 extern "C" {
 

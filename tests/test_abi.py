@@ -132,19 +132,49 @@ def test_tuned_config_table():
     assert B.bs_set_tuned_config(0, 4, 41, 16, 16, 1, 0) == B.BS_EINVAL  # size class
     assert B.bs_set_tuned_config(0, 4, 28, 16, 4, 1, 0) == B.BS_EINVAL   # shape not compiled
     assert B.bs_clear_tuned_configs() == B.BS_OK
-    from paper_2106_06161_amd import autotune
-
-    autotune.apply(autotune.load())
+    assert B.bs_load_tuned_configs(B.TUNED_FILE) == B.BS_OK
 
 
 def test_shipped_tuned_table_is_valid():
     from paper_2106_06161_amd import autotune
 
-    entries = autotune.load()
+    entries = autotune.read_table()
+    assert len(entries) >= 90
+    shapes = [tuple(s) for s in autotune.SHAPES + autotune.COMPACT_SHAPES]
     for e in entries:
-        shapes = [tuple(s) for s in autotune.SHAPES + autotune.COMPACT_SHAPES]
-        assert (e["waves"], e["items"], e["depth"]) in shapes
-    assert autotune.apply(entries) == len(entries)
+        assert (e["waves"], e["items"], e["depth"]) in shapes and e["grid_mult"] in autotune.GRIDS
+    assert B.bs_load_tuned_configs(B.TUNED_FILE) == B.BS_OK
+    # the table decides the launch shape the library reports
+    e = next(e for e in entries if e["kind"] == 0 and e["elem_bytes"] == 4 and e["size_bits"] == 28)
+    assert B.bs_query_config(0, 4, (1 << 27) + 1) == (e["waves"], e["items"], e["depth"], e["grid_mult"])
+
+
+def test_tuned_table_files_round_trip(tmp_path):
+    """Saving and loading a table keeps every entry; a malformed or
+    non-compiled entry is rejected and leaves the table unchanged."""
+    from paper_2106_06161_amd import autotune
+
+    assert B.bs_load_tuned_configs(B.TUNED_FILE) == B.BS_OK
+    out = tmp_path / "t.txt"
+    assert B.bs_save_tuned_configs(str(out)) == B.BS_OK
+    key = lambda e: (e["kind"], e["elem_bytes"], e["size_bits"], e["waves"], e["items"], e["depth"], e["grid_mult"])
+    assert sorted(map(key, autotune.read_table(str(out)))) == sorted(map(key, autotune.read_table()))
+    before = B.bs_query_config(0, 4, (1 << 27) + 1)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("arch gfx950\n0 4 28 16 4 1 0\n")  # 16 waves x 4 items is not compiled
+    assert B.bs_load_tuned_configs(str(bad)) == B.BS_EINVAL
+    bad.write_text("0 4 28 16\n")
+    assert B.bs_load_tuned_configs(str(bad)) == B.BS_EINVAL
+    assert B.bs_load_tuned_configs(str(tmp_path / "missing.txt")) == B.BS_EINVAL
+    assert B.bs_query_config(0, 4, (1 << 27) + 1) == before
+
+
+def test_autotune_without_a_device():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present (the GPU test runs the tuner)")
+    assert B.bs_autotune(0, None) == B.BS_ENODEV
 
 
 def test_permutation_and_unshuffle_argument_checks():
@@ -179,3 +209,19 @@ def test_xcd_mode_argument_check():
     assert B.bs_probe_set_xcd_mode(3) == B.BS_EINVAL
     for m in (0, 1, 2):
         assert B.bs_probe_set_xcd_mode(m) == B.BS_OK
+
+
+def test_tuned_lookup_falls_back_to_nearest_class():
+    try:
+        assert B.bs_clear_tuned_configs() == B.BS_OK
+        assert B.bs_set_tuned_config(0, 4, 20, 8, 8, 2, 1) == B.BS_OK
+        assert B.bs_set_tuned_config(0, 4, 24, 16, 8, 9, 1) == B.BS_OK
+        assert B.bs_set_tuned_config(0, 8, 30, 16, 16, 1, 2) == B.BS_OK
+        assert B.bs_query_config(0, 4, 1 << 24) == (16, 8, 9, 1)
+        assert B.bs_query_config(0, 4, 1 << 22) == (8, 8, 2, 1)        # largest class below
+        assert B.bs_query_config(0, 4, (1 << 31) + 1) == (16, 8, 9, 1)  # k = 32: still below
+        assert B.bs_query_config(0, 4, 100) == (8, 8, 2, 1)            # smallest class above
+        assert B.bs_query_config(0, 8, 1 << 20) == (16, 16, 1, 2)      # other element size's own entries
+        assert B.bs_query_config(0, 16, 1 << 20) == B.bs_get_config()  # none for this size: default
+    finally:
+        B.bs_load_tuned_configs(B.TUNED_FILE)
