@@ -25,6 +25,8 @@ talks to the Executor interface below.
 from __future__ import annotations
 
 import dataclasses
+import gc
+import heapq
 import math
 import sys
 import time
@@ -71,7 +73,7 @@ class Executor(Protocol):
     one element size; `poll` returns True once its results are final."""
 
     def place(self, req: Request) -> None: ...
-    def launch(self, reqs: list[Request]) -> object: ...
+    def launch(self, reqs: list[Request], lane: int = 1) -> object: ...  # lane 0: small groups, 1: large
     def poll(self, handle: object) -> bool: ...
     def results(self, handle: object) -> dict[int, object]: ...
     def release(self, handle: object) -> None: ...
@@ -104,6 +106,7 @@ class ServeReport:
             "latency_p90_ms": float(np.percentile(lat, 90) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
             "latency_max_ms": float(lat.max() * 1e3),
+            **self._by_size(ok),
             "launches": self.launches,
             "batched_launches": self.batched_launches,
             "mean_requests_per_launch": len(self.completions) / max(self.launches, 1),
@@ -112,22 +115,53 @@ class ServeReport:
         }
 
 
+    @staticmethod
+    def _by_size(ok: list[Completion]) -> dict:
+        """p50 / p99 latency of requests up to 10^6 records and above."""
+        out = {}
+        for name, sel in (("le_1e6", lambda n: n <= 1_000_000), ("gt_1e6", lambda n: n > 1_000_000)):
+            lat = np.array([c.latency for c in ok if sel(c.request.n)])
+            if lat.size:
+                out[f"latency_p50_{name}_ms"] = float(np.percentile(lat, 50) * 1e3)
+                out[f"latency_p99_{name}_ms"] = float(np.percentile(lat, 99) * 1e3)
+        return out
+
+
 class _Grouper:
     """Admitted requests on their way to launches: a request above small_items
     is a launch of its own; smaller ones are coalesced per element size, in
     admission order, up to max_requests requests and max_items records per
-    launch.  Closed groups wait in `ready` (FIFO); flush() closes the open ones.
-    Every operation is O(1) per request."""
+    launch.  flush() closes the open small groups.
 
-    def __init__(self, small_items: int, max_requests: int, max_items: int):
+    Launch order.  policy "fifo": closed launches in the order they closed.
+    policy "size": closed small-request groups first (in order), then single
+    large requests shortest first, except that a large request admitted at
+    least max_wait seconds ago goes first, so none starves.  O(log n) per
+    request (heap and queue entries of launched requests are dropped lazily)."""
+
+    def __init__(self, small_items: int, max_requests: int, max_items: int, policy: str = "size",
+                 max_wait: float = 0.05):
+        if policy not in ("fifo", "size"):
+            raise ValueError(f"unknown launch policy {policy!r}")
         self.small_items, self.max_requests, self.max_items = small_items, max_requests, max_items
-        self.ready: deque[list[Request]] = deque()
+        self.policy, self.max_wait = policy, max_wait
+        self.ready: deque[list[Request]] = deque()  # fifo: every closed launch; size: small groups
+        self.big: dict[int, Request] = {}  # size: large requests not launched yet, by sequence number
+        self.by_size: list[tuple[int, int]] = []  # size: heap of (records, seq)
+        self.by_age: deque[tuple[float, int]] = deque()  # size: (admitted, seq) in admission order
+        self.seq = 0
         self.open: dict[int, list[Request]] = {}
         self.open_items: dict[int, int] = {}
 
-    def add(self, r: Request) -> None:
+    def add(self, r: Request, now: float = 0.0) -> None:
         if r.n > self.small_items:
-            self.ready.append([r])
+            if self.policy == "fifo":
+                self.ready.append([r])
+            else:
+                self.big[self.seq] = r
+                heapq.heappush(self.by_size, (r.n, self.seq))
+                self.by_age.append((now, self.seq))
+                self.seq += 1
             return
         eb = r.elem_bytes
         cur = self.open.setdefault(eb, [])
@@ -139,26 +173,49 @@ class _Grouper:
         self.open_items[eb] = self.open_items.get(eb, 0) + r.n
 
     def flush(self) -> None:
-        for eb, cur in self.open.items():
+        for cur in self.open.values():
             if cur:
                 self.ready.append(cur)
         self.open.clear()
         self.open_items.clear()
 
+    def pop(self, now: float = 0.0, allow_big: bool = True) -> list[Request] | None:
+        """The next closed launch, or None (allow_big=False: small groups only)."""
+        if self.ready:
+            return self.ready.popleft()
+        if not allow_big or not self.big:
+            return None
+        while self.by_age[0][1] not in self.big:
+            self.by_age.popleft()
+        if now - self.by_age[0][0] >= self.max_wait:
+            return [self.big.pop(self.by_age.popleft()[1])]
+        while True:
+            _, seq = heapq.heappop(self.by_size)
+            if seq in self.big:
+                return [self.big.pop(seq)]
+
+    def has_closed(self) -> bool:
+        return bool(self.ready) or bool(self.big)
+
     def __bool__(self) -> bool:
-        return bool(self.ready) or any(self.open.values())
+        return bool(self.ready) or bool(self.big) or any(self.open.values())
 
 
 class ShuffleServer:
     def __init__(self, executor: Executor, budget_bytes: int, small_items: int = 1 << 20,
                  max_batch_requests: int = 2048, max_batch_items: int = 1 << 26, max_inflight: int = 16,
-                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+                 policy: str = "size", max_wait: float = 0.05, small_slots: int = 2):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.small_items = small_items
         self.max_batch_requests = max_batch_requests
         self.max_batch_items = max_batch_items
         self.max_inflight = max_inflight
+        self.policy = policy
+        self.max_wait = max_wait
+        # "size": launch slots large requests may not take, kept for small groups
+        self.small_slots = min(small_slots, max_inflight - 1) if policy == "size" else 0
         self.clock = clock
         self.sleep = sleep
         self.cancelled: set[int] = set()
@@ -168,8 +225,20 @@ class ShuffleServer:
         self.cancelled.add(request_id)
 
     def run(self, requests: list[Request], on_result: Callable[[Request, object], None] | None = None) -> ServeReport:
+        # no cyclic-GC pauses inside the scheduling loop (the request objects
+        # hold no cycles; reference counting still frees them)
+        gc_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, on_result)
+        finally:
+            if gc_enabled:
+                gc.enable()
+
+    def _run(self, requests: list[Request], on_result: Callable[[Request, object], None] | None) -> ServeReport:
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.id)))
-        grouper = _Grouper(self.small_items, self.max_batch_requests, self.max_batch_items)
+        grouper = _Grouper(self.small_items, self.max_batch_requests, self.max_batch_items, self.policy,
+                           self.max_wait)
         admit_time: dict[int, float] = {}
         inflight: list[tuple[object, list[Request]]] = []
         completions: list[Completion] = []
@@ -226,15 +295,21 @@ class ShuffleServer:
                     reserved -= r.out_bytes
                     completions.append(Completion(r, now, self.clock() - t0, 0, f"{type(exc).__name__}: {exc}"))
                     continue
-                grouper.add(r)
+                grouper.add(r, now)
             # launch what is admitted, as slots allow; open small groups are
             # closed only when a slot is free for them
             while grouper and len(inflight) < self.max_inflight:
-                if not grouper.ready:
+                # "size": small requests go out as soon as a slot is free;
+                # "fifo": open groups close only when nothing else is ready
+                if self.policy == "size" or not grouper.has_closed():
                     grouper.flush()
-                g = grouper.ready.popleft()
+                big_ok = len(inflight) < self.max_inflight - self.small_slots
+                g = grouper.pop(self.clock() - t0, allow_big=big_ok)
+                if g is None:
+                    break
+                small = len(g) > 1 or g[0].n <= self.small_items
                 try:
-                    handle = self.ex.launch(g)
+                    handle = self.ex.launch(g, lane=0 if (small and self.policy == "size") else 1)
                 except Exception as exc:
                     t_fail = self.clock() - t0
                     for r in g:
@@ -301,10 +376,16 @@ class HipExecutor:
         eb, first = self.where[req.id]
         return self.pools[eb][first:first + req.n]
 
-    def launch(self, reqs: list[Request]):
+    def launch(self, reqs: list[Request], lane: int = 1):
         torch, bs = self.torch, self.bs
-        stream = self.streams[self.next_stream]
-        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        # lane 0 (coalesced small requests) has the first stream to itself, so
+        # small launches never queue behind a large one; large launches take
+        # the other streams in turn
+        if lane == 0 or len(self.streams) == 1:
+            stream = self.streams[0]
+        else:
+            stream = self.streams[1 + self.next_stream % (len(self.streams) - 1)]
+            self.next_stream += 1
         eb = reqs[0].elem_bytes
         firsts = [self.where[r.id][1] for r in reqs]
         contiguous = all(firsts[i] + reqs[i].n == firsts[i + 1] for i in range(len(reqs) - 1))
@@ -376,10 +457,15 @@ def main(argv=None) -> int:
     p.add_argument("--streams", type=int, default=4)
     p.add_argument("--rounds", type=int, default=24)
     p.add_argument("--seed", type=int, default=5)
+    p.add_argument("--policy", choices=("size", "fifo"), default="size")
+    p.add_argument("--max-inflight", type=int, default=16)
+    p.add_argument("--small-slots", type=int, default=2)
     a = p.parse_args(argv)
     ex = HipExecutor(streams=a.streams, rounds=a.rounds)
-    server = ShuffleServer(ex, int(a.budget_gib * 2**30))
-    out = {"requests": a.requests}
+    server = ShuffleServer(ex, int(a.budget_gib * 2**30), policy=a.policy, max_inflight=a.max_inflight,
+                           small_slots=a.small_slots)
+    out = {"requests": a.requests, "policy": a.policy, "max_inflight": a.max_inflight,
+           "small_slots": a.small_slots, "streams": a.streams}
     if a.qps > 0:
         rates = [a.qps]
     else:

@@ -39,6 +39,7 @@ class FakeExecutor:
         self.fail_poll_ids = set(fail_poll_ids)
         self.fail_launch_ids = set(fail_launch_ids)
         self.launches = []
+        self.lanes = []
         self.live = 0
         self.max_live = 0
 
@@ -53,7 +54,8 @@ class FakeExecutor:
         eb, first = self.where[r.id]
         return self.pools[eb][first:first + r.n]
 
-    def launch(self, reqs):
+    def launch(self, reqs, lane=1):
+        self.lanes.append(lane)
         if any(r.id in self.fail_launch_ids for r in reqs):
             raise RuntimeError("launch failed")
         self.launches.append([r.id for r in reqs])
@@ -182,7 +184,7 @@ class _InstantExecutor:
     def place(self, r):
         pass
 
-    def launch(self, reqs):
+    def launch(self, reqs, lane=1):
         self.k += 1
         return [self.k, 0]
 
@@ -210,3 +212,41 @@ def test_scheduler_cost_is_linear_in_requests():
     s = rep.summary()
     assert s["completed"] == 50_000 and s["failed"] == 0
     assert dt < 10.0, dt
+
+
+def test_size_policy_launches_small_groups_first_then_shortest():
+    ex = FakeExecutor(polls_to_finish=3)
+    sizes = [9000, 3000, 50, 7000, 60, 5000]
+    rs = reqs(sizes, gap=0.0)
+    server(ex, 1 << 30, small_items=1000, max_inflight=2, small_slots=1, policy="size", max_wait=1e9).run(rs)
+    # one slot for large requests: the small group first, then large ones by size
+    assert ex.launches[0] == [2, 4] and ex.lanes[0] == 0
+    big = [g[0] for g in ex.launches[1:]]
+    assert big == [1, 5, 3, 0] and all(lane == 1 for lane in ex.lanes[1:])
+
+
+def test_size_policy_ages_out_long_waits():
+    ex = FakeExecutor(polls_to_finish=400)
+    # request 0 (largest) arrives first; with max_wait 0 it is launched first
+    rs = reqs([9000, 3000, 5000], gap=0.0)
+    server(ex, 1 << 30, small_items=1000, max_inflight=2, small_slots=1, policy="size", max_wait=0.0).run(rs)
+    assert [g[0] for g in ex.launches] == [0, 1, 2]
+
+
+def test_fifo_policy_keeps_admission_order():
+    ex = FakeExecutor(polls_to_finish=3)
+    rs = reqs([9000, 3000, 7000, 5000], gap=0.0)
+    server(ex, 1 << 30, small_items=1000, max_inflight=1, policy="fifo").run(rs)
+    assert [g[0] for g in ex.launches] == [0, 1, 2, 3]
+    assert set(ex.lanes) == {1}
+
+
+def test_small_slots_keep_room_for_small_groups():
+    ex = FakeExecutor(polls_to_finish=50)
+    rs = reqs([5000] * 8 + [10, 20], gap=0.0)
+    srv = server(ex, 1 << 30, small_items=1000, max_inflight=4, small_slots=2, policy="size")
+    rep = srv.run(rs)
+    assert len(rep.ok()) == 10
+    # the small group was launched while large requests were still waiting
+    first_small = next(i for i, g in enumerate(ex.launches) if g == [8, 9])
+    assert first_small < 8
