@@ -10,14 +10,21 @@
 // Per tile:
 //   1. cipher: ITEMS VariablePhilox evaluations per lane, interleaved for ILP;
 //   2. keep = index < 2^k and f(index) < n; ballot -> wave-local ranks;
-//   3. the random gathers in[f(i)] are issued at once, so their latency
-//      overlaps the scan below;
-//   4. wave counts -> LDS -> tile total; wavefront 0 runs the decoupled
+//   3. wave counts -> LDS -> tile total; wavefront 0 runs the decoupled
 //      look-back for the tile's exclusive prefix;
-//   5. kept items are stored at out[prefix + rank]: each item step of a
-//      wavefront writes one contiguous run of the output.
-// Tiles are handed out by an atomic ticket in launch order, so a tile only
-// ever waits on tiles already owned by running workgroups.
+//   4. the random gathers in[f(i)] and the stores at out[prefix + rank].
+// Two schedules implement steps 3-4:
+//   register  each lane keeps its own kept records in registers: the gathers
+//             are issued right after the cipher (their latency overlaps the
+//             scan) and every item step of a wavefront stores one contiguous
+//             run (shuffle_single_kernel, shuffle_batched_kernel);
+//   compacted the tile's kept images are first written to LDS in rank order,
+//             then all lanes gather and store consecutive ranks, so memory
+//             instructions run with full wavefronts; optionally the next
+//             tile's cipher runs while the current tile's gathers are in
+//             flight (shuffle_compact_kernel, shuffle_batched_compact_kernel).
+// Tiles are handed out by atomic tickets in tile order, so a tile only ever
+// waits on tiles already owned by running workgroups.
 #pragma once
 
 #include <hip/hip_runtime.h>
