@@ -130,8 +130,37 @@ def committed_traffic(digest: str, launch: dict):
     return rec
 
 
-def cpu_baseline() -> dict:
-    """The oracle, single thread, on a bounded sample of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _pinned_trials(fn, trials: int) -> list[float]:
+    """Runs fn `trials` times with this thread pinned to one core (restored after)."""
+    old = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    if old:
+        os.sched_setaffinity(0, {min(old)})
+    try:
+        times = []
+        for _ in range(trials):
+            t0 = time.perf_counter()
+            fn()
+            times.append(time.perf_counter() - t0)
+        return times
+    finally:
+        if old:
+            os.sched_setaffinity(0, old)
+
+
+def cpu_baseline(trials: int = 5) -> dict:
+    """The oracle, single thread pinned to one core, on a bounded sample of the
+    same workload: mean of `trials` runs."""
     import numpy as np
 
     import oracle
@@ -139,32 +168,33 @@ def cpu_baseline() -> dict:
 
     n = (1 << 25) + 1  # same padding ratio as the headline (domain 2^26)
     x = W.uniform_u32(n, seed=SEED)
-    t0 = time.perf_counter()
     out = oracle.shuffle(x, SEED, ROUNDS)
-    dt = time.perf_counter() - t0
     assert out.shape == x.shape and np.uint64(out.sum(dtype=np.uint64)) == np.uint64(x.sum(dtype=np.uint64))
+    times = _pinned_trials(lambda: oracle.shuffle(x, SEED, ROUNDS), trials)
+    dt = sum(times) / len(times)
     return {
         "value": n / dt / 1e9,
         "unit": "Gelem/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"n=2^25+1 uint32 uniform (PCG64 seed 7), seed 7, {ROUNDS} rounds, domain 2^26, one run "
-                  f"({dt:.1f} s) on {platform.processor() or platform.machine()}",
+        "sample": f"n=2^25+1 uint32 uniform (PCG64 seed 7), seed 7, {ROUNDS} rounds, domain 2^26; mean of "
+                  f"{trials} runs ({dt:.2f} s each, min {min(times):.2f} s) pinned to one core of {cpu_model()} "
+                  f"({os.cpu_count()} logical CPUs)",
     }
 
 
-def cpu_std_shuffle() -> dict:
-    """std::shuffle (Fisher-Yates, std::mt19937_64), one thread, same sample bytes."""
+def cpu_std_shuffle(trials: int = 5) -> dict:
+    """std::shuffle (Fisher-Yates, std::mt19937_64), one thread pinned to one core, same sample bytes."""
     import oracle
     from paper_2106_06161_amd import workloads as W
 
     n = (1 << 25) + 1
     x = W.uniform_u32(n, seed=SEED)
-    t0 = time.perf_counter()
-    oracle.std_shuffle_u32(x, SEED)
-    dt = time.perf_counter() - t0
+    times = _pinned_trials(lambda: oracle.std_shuffle_u32(x, SEED), trials)
+    dt = sum(times) / len(times)
     return {"value": n / dt / 1e9, "unit": "Gelem/s", "cores": 1, "kind": "std::shuffle",
-            "sample": f"n=2^25+1 uint32 (same bytes as cpu_baseline), std::mt19937_64(7), one run ({dt:.2f} s)"}
+            "sample": f"n=2^25+1 uint32 (same bytes as cpu_baseline), std::mt19937_64(7), mean of {trials} runs "
+                      f"({dt:.3f} s each) pinned to one core of {cpu_model()}"}
 
 
 def bench_batched(torch, bs, W, np, dev, stream, timer, rounds) -> dict:
@@ -489,6 +519,8 @@ def main() -> int:
         ceil["gather_index_array_Gelem_s"] = N_HEADLINE / t / 1e9
         t = timer.run(lambda: B.bs_probe_cipher_scan(N_HEADLINE, SEED, rounds, ws.data_ptr(), ws.numel(), sp), 10)
         ceil["cipher_scan_only_ms"] = t * 1e3
+        t = timer.run(lambda: B.bs_probe_cipher_scan(N_HEADLINE, SEED, 4, ws.data_ptr(), ws.numel(), sp), 10)
+        ceil["cipher_scan_only_4_rounds_ms"] = t * 1e3
         t4 = timer.run(lambda: bs.shuffle(x, SEED, 4, out=y, workspace=ws), 10)
         ceil["shuffle_4_rounds_ms"] = t4 * 1e3
         ceil["shuffle_4_rounds_Gelem_s"] = N_HEADLINE / t4 / 1e9
