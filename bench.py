@@ -95,6 +95,8 @@ def parse_args():
     p.add_argument("--serve-requests", type=int, default=2000)
     p.add_argument("--profile", action="store_true",
                    help="profiler run: one copy of known size, then the steps; no extras")
+    p.add_argument("--profile-batched", action="store_true",
+                   help="profiler run of the batched workload: --steps batched launches, no extras")
     return p.parse_args()
 
 
@@ -414,6 +416,22 @@ def main() -> int:
     sp = stream.cuda_stream
     timer = Timer(torch, stream)
     rounds = args.rounds
+
+    if args.profile_batched:
+        b = W.batch(4096, 100, 1_000_000, seed=3)
+        total = b["total"]
+        xb = torch.arange(total, dtype=torch.int64, device=dev).to(torch.int32)
+        yb = torch.empty_like(xb)
+        off = torch.from_numpy(b["offsets"]).to(dev)
+        sd = torch.from_numpy(b["seeds"].view(np.int64)).to(dev)
+        wsb = bs.make_workspace(bs.workspace_bytes(total, 4096), device=dev)
+        for _ in range(args.warmup + args.steps):
+            bs.shuffle_batched(xb, off, sd, rounds, out=yb, workspace=wsb)
+        torch.cuda.synchronize()
+        err = bs.workspace_error(wsb)
+        log(f"bench: {args.warmup + args.steps} batched launches, launch {B.bs_query_config(1, 4, total, 4096)}, "
+            f"device status {err}")
+        return 1 if err else 0
 
     log("bench: generating the headline input (n=2^27+1 uint32, PCG64 seed 7)")
     x_np = W.uniform_u32(N_HEADLINE, seed=SEED)
