@@ -186,3 +186,38 @@ def test_headline_workload_24_rounds_slices():
 def test_power_of_two_control_24_rounds_slices():
     x = W.uniform_u32(1 << 27, seed=7)
     _check_large(x, 7, 24)
+
+
+@pytest.mark.parametrize("cfg", [(0, 0, 0, 0), (16, 16, 9, 0), (16, 16, 1, 0)])
+def test_single_shuffles_under_graph_replay(cfg):
+    """Several bs_shuffle calls captured in one HIP graph and replayed: every
+    replay, with eager launches on the same workspace between replays, equals
+    the oracle."""
+    assert B.bs_set_config(*cfg) == B.BS_OK
+    sizes = [1000, 100_003, 1 << 20, (1 << 22) + 1]
+    xs = [W.uniform_u32(n, seed=n) for n in sizes]
+    want = [oracle.shuffle(x, 40 + i, 24) for i, x in enumerate(xs)]
+    xd = [torch.from_numpy(x).to(DEV) for x in xs]
+    outs = [torch.empty_like(x) for x in xd]
+    ws = bs.make_workspace(bs.workspace_bytes(max(sizes)), device=DEV)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        for i, x in enumerate(xd):
+            bs.shuffle(x, 40 + i, 24, out=outs[i], workspace=ws)
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for i, x in enumerate(xd):
+            bs.shuffle(x, 40 + i, 24, out=outs[i], workspace=ws)
+    for rep in range(5):
+        for o in outs:
+            o.fill_(0)
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), want[i]), (cfg, rep, sizes[i])
+        bs.shuffle(xd[1], 7, 24, workspace=ws)  # eager work on the same workspace between replays
+        torch.cuda.synchronize()
+    assert bs.workspace_error(ws) == B.BS_OK
