@@ -115,9 +115,10 @@ bs_status bs_workspace_error(void *workspace, void *stream);
  *   rounds      0..64.  0 gives the identity permutation (out = in).
  *   workspace   device memory of workspace_bytes >= bs_workspace_bytes(n,0,eb)
  *               prepared by bs_workspace_init, or NULL to use the library's
- *               per-(device, stream) cache (grown with hipMalloc when needed;
- *               returns BS_EINVAL if it would have to grow while `stream` is
- *               being captured into a graph).
+ *               per-(device, stream) cache (grown with hipMalloc when needed).
+ *               A call captured into a graph must pass its own workspace
+ *               (NULL while `stream` is capturing returns BS_EINVAL: a later
+ *               call could regrow the cache under the captured graph).
  *   stream      hipStream_t as void*.
  *
  * Writes out[rank(i)] = in[f(i)] for every padded index i < 2^k with f(i) < n.

@@ -127,7 +127,7 @@ bs_status device_cus(int dev, uint32_t* cus) {
 }
 
 // Resolves the workspace for a call: the caller's, or the library's cache
-// entry for (device, stream), grown when too small.
+// entry for (device, stream), grown when too small (never while capturing).
 bs_status resolve_workspace(void* user, size_t user_bytes, size_t need, hipStream_t stream, void** ws) {
   if (user) {
     if (user_bytes < need) return BS_ENOMEM;
@@ -135,18 +135,20 @@ bs_status resolve_workspace(void* user, size_t user_bytes, size_t need, hipStrea
     *ws = user;
     return BS_OK;
   }
+  // A captured call must bring its own workspace: the cache may be regrown
+  // (freed and reallocated) by a later call, under the captured graph.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(stream, &cap);
+  if (e != hipSuccess) return hip_fail(e);
+  if (cap != hipStreamCaptureStatusNone) return BS_EINVAL;
   int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
+  e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
   CacheEntry& c = g_cache[{dev, stream}];
   if (c.bytes >= need) {
     *ws = c.ptr;
     return BS_OK;
   }
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  e = hipStreamIsCapturing(stream, &cap);
-  if (e != hipSuccess) return hip_fail(e);
-  if (cap != hipStreamCaptureStatusNone) return BS_EINVAL;  // cannot allocate during capture
   size_t bytes = std::max(need, size_t(1) << 20);
   if (c.ptr) {
     e = hipStreamSynchronize(stream);

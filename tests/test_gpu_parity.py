@@ -221,3 +221,19 @@ def test_single_shuffles_under_graph_replay(cfg):
         bs.shuffle(xd[1], 7, 24, workspace=ws)  # eager work on the same workspace between replays
         torch.cuda.synchronize()
     assert bs.workspace_error(ws) == B.BS_OK
+
+
+def test_capture_without_a_workspace_is_rejected():
+    """During graph capture the library's own workspace cache is not used
+    (a later call could regrow it under the graph): BS_EINVAL, nothing captured."""
+    x = torch.arange(1000, dtype=torch.int32, device=DEV)
+    y = torch.empty_like(x)
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        st = B.bs_shuffle(x.data_ptr(), y.data_ptr(), 1000, 4, 1, 24, None, 0, stream.cuda_stream)
+        y.fill_(3)  # something to capture
+    assert st == B.BS_EINVAL
+    g.replay()
+    torch.cuda.synchronize()
+    assert bool((y == 3).all())
