@@ -359,18 +359,9 @@ bs_status bs_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t k = bs_domain_bits(n);
   bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, rounds);
   a.in = static_cast<const uint8_t*>(in);
   a.out = static_cast<uint8_t*>(out);
-  a.n = n;
-  a.domain = uint64_t(1) << k;
-  a.cs.w = k / 2;
-  a.cs.r = k - a.cs.w;
-  a.cs.wmask = (1u << a.cs.w) - 1u;
-  a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
-  a.rounds = rounds;
-  bs_round_keys(seed, rounds, a.key);
-  for (uint32_t r = 0; r < rounds; ++r) a.key[r] &= a.cs.wmask;  // only the half width reaches the state
-  a.key[rounds] = 0;
 
   std::lock_guard<std::mutex> lock(g_mu);
   const bsd::LaunchConfig cfg = pick_config(0, elem_bytes, k);
