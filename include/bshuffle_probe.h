@@ -54,6 +54,19 @@ bs_status bs_probe_shuffle_unfused(const void *in, void *out, uint64_t n, uint32
                                    size_t workspace_bytes, void *stream);
 
 /*
+ * bs_probe_set_watchdog -- failure-path testing of the look-back.  spin_limit:
+ * polls after which a look-back wait gives up (0 restores the default, about
+ * seconds of polling); the launch then records BS_ETIMEOUT for
+ * bs_workspace_error, takes the nearest predecessor as a prefix of 0 and still
+ * finishes, with every store kept inside `out`.  stall_first_tile = 1 makes
+ * the first tile of every shuffle (and batch segment) withhold its status
+ * word, so the next tile's wait deterministically runs into the limit; the
+ * output is then wrong by design.  BS_EINVAL for stall_first_tile > 1.
+ * Applies to every later launch from every thread.
+ */
+bs_status bs_probe_set_watchdog(uint32_t spin_limit, uint32_t stall_first_tile);
+
+/*
  * bs_probe_set_xcd_mode -- how batched launches place segments on the 8 XCDs
  * (never changes results).  1: the batch's tiles are split into 8 ranges of
  * whole segments with about equal tile counts; workgroups take tiles from the

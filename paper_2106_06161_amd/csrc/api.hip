@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <iterator>
 #include <map>
 #include <mutex>
@@ -59,6 +60,14 @@ bsd::LaunchConfig pick_config(uint32_t kind, uint32_t elem_bytes, uint32_t bits)
 }
 bool g_nontemporal_store = false;
 uint32_t g_xcd_mode = 2;  // batched tile ranges per XCD: 0 off, 1 on, 2 automatic
+// look-back watchdog of later launches (spin limit, stall test hook); atomics
+// so the entry points can read them without the lock
+std::atomic<uint32_t> g_spin_limit{bsd::kSpinLimit};
+std::atomic<uint32_t> g_stall_first{0};
+
+bsd::Watchdog current_watchdog() {
+  return {g_spin_limit.load(std::memory_order_relaxed), g_stall_first.load(std::memory_order_relaxed)};
+}
 
 struct CacheEntry {
   void* ptr = nullptr;
@@ -186,6 +195,7 @@ void setup_cipher(bsd::SingleArgs& a, uint64_t n, uint64_t seed, uint32_t rounds
   uint64_t st = seed;
   for (uint32_t r = 0; r < rounds; ++r) a.key[r] = uint32_t(splitmix64_step(st)) & a.cs.wmask;
   a.key[rounds] = 0;
+  a.wd = current_watchdog();
 }
 
 bool ranges_overlap(const void* a, const void* b, uint64_t bytes) {
@@ -418,6 +428,7 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
   a.capacity = uint32_t(lay.capacity);
   a.tile = 64u * cfg.waves * cfg.items;
   a.nontemporal = g_nontemporal_store ? 1u : 0u;
+  a.wd = current_watchdog();
   a.xcd_mode = g_xcd_mode;
   a.hdr = reinterpret_cast<bsd::WorkspaceHeader*>(base);
   a.status = reinterpret_cast<uint64_t*>(base + lay.status);
@@ -444,6 +455,13 @@ extern "C" bs_status bs_probe_set_xcd_mode(uint32_t mode) {
   return BS_OK;
 }
 
+extern "C" bs_status bs_probe_set_watchdog(uint32_t spin_limit, uint32_t stall_first_tile) {
+  if (stall_first_tile > 1) return BS_EINVAL;
+  g_spin_limit.store(spin_limit ? spin_limit : bsd::kSpinLimit, std::memory_order_relaxed);
+  g_stall_first.store(stall_first_tile, std::memory_order_relaxed);
+  return BS_OK;
+}
+
 extern "C" bs_status bs_probe_set_store_mode(uint32_t nontemporal) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_nontemporal_store = nontemporal != 0;
@@ -457,16 +475,7 @@ extern "C" bs_status bs_probe_cipher_scan(uint64_t n, uint64_t seed, uint32_t ro
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t k = bs_domain_bits(n);
   bsd::SingleArgs a = {};
-  a.n = n;
-  a.domain = uint64_t(1) << k;
-  a.cs.w = k / 2;
-  a.cs.r = k - a.cs.w;
-  a.cs.wmask = (1u << a.cs.w) - 1u;
-  a.cs.rmask = uint32_t((uint64_t(1) << a.cs.r) - 1u);
-  a.rounds = rounds;
-  bs_round_keys(seed, rounds, a.key);
-  for (uint32_t r = 0; r < rounds; ++r) a.key[r] &= a.cs.wmask;
-  a.key[rounds] = 0;
+  setup_cipher(a, n, seed, rounds);
   std::lock_guard<std::mutex> lock(g_mu);
   const bsd::LaunchConfig cfg = g_cfg;
   const uint64_t tile = k > 32 ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;

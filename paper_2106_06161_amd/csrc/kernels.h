@@ -22,6 +22,7 @@ struct SingleArgs {
   uint32_t num_tiles;  // ceil(domain / tile)
   uint32_t capacity;   // status words the workspace holds
   uint32_t nontemporal;  // 1: output stores bypass cache retention
+  Watchdog wd;           // look-back spin limit (and the stall test hook)
   WorkspaceHeader* hdr;
   uint64_t* status;
   const uint32_t* table;        // unfused variant: f over the padded domain
@@ -50,6 +51,7 @@ struct BatchArgs {
   uint32_t capacity;        // status words the workspace holds (= max tiles)
   uint32_t tile;            // indices per tile of the launch configuration
   uint32_t nontemporal;     // 1: output stores bypass cache retention
+  Watchdog wd;              // look-back spin limit (and the stall test hook)
   uint32_t xcd_mode;        // tile ranges per XCD: 0 off, 1 on, 2 when segments average
                             // at least kXcdMinTilesPerSegment tiles
   WorkspaceHeader* hdr;

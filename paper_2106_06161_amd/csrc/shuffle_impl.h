@@ -303,7 +303,8 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, MODE, ITEMS, WIDE>& 
 template <int WAVES, bool LOOKBACK = true, bool XCD = false>
 __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* status, uint32_t status_first,
                                               uint32_t status_idx, uint32_t tag, WorkspaceHeader* hdr,
-                                              TileLds<WAVES>& lds, const uint64_t* tile_prefix = nullptr) {
+                                              TileLds<WAVES>& lds, Watchdog wd,
+                                              const uint64_t* tile_prefix = nullptr) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (lane == 0) lds.wave_count[wave] = wave_count;
@@ -319,7 +320,7 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
   if (wave == 0) {
     uint64_t ex;
     if constexpr (LOOKBACK)
-      ex = lookback_exclusive_prefix(status, status_first, status_idx, tag, uint64_t(tile_total), &hdr->error);
+      ex = lookback_exclusive_prefix(status, status_first, status_idx, tag, uint64_t(tile_total), &hdr->error, wd);
     else
       ex = tile_prefix[status_idx];
     if (lane == 0) lds.tile_exclusive = ex;
@@ -393,7 +394,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
       tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile,
                                                           a.table, a.lcg_a, a.lcg_c);
       const uint64_t prefix =
-          tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.tile_prefix);
+          tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.wd,
+                                     a.tile_prefix);
       tile_store(cur, a.in, a.out, a.n, prefix, nt);
       tile = lds.next_ticket;
     }
@@ -403,8 +405,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
     if (tile < a.num_tiles) {
       tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile,
                                                           a.table, a.lcg_a, a.lcg_c);
-      cur_prefix =
-          tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.tile_prefix);
+      cur_prefix = tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.wd,
+                                              a.tile_prefix);
     }
     while (tile < a.num_tiles) {
       const uint32_t next = lds.next_ticket;
@@ -414,8 +416,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
                                                             a.table, a.lcg_a, a.lcg_c);
       tile_store(cur, a.in, a.out, a.n, cur_prefix, nt);
       if (more) {
-        cur_prefix =
-            tile_scan<WAVES, LOOKBACK>(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds, a.tile_prefix);
+        cur_prefix = tile_scan<WAVES, LOOKBACK>(nxt.wave_count, a.status, 0u, next, tag, a.hdr, lds, a.wd,
+                                                a.tile_prefix);
         cur = nxt;
       }
       tile = next;
@@ -464,7 +466,8 @@ template <int EB, int WAVES, int ITEMS, bool PIPE, bool LOOKBACK, bool XCD, type
 __device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTile<4, kIndices, ITEMS, false>& c,
                                                  WorkspaceHeader* hdr, uint64_t* status,
                                                  const uint64_t* tile_prefix, uint32_t tag, bool nt,
-                                                 CompactLds<WAVES, ITEMS>& lds, NextCipher&& next_cipher) {
+                                                 CompactLds<WAVES, ITEMS>& lds, Watchdog wd,
+                                                 NextCipher&& next_cipher) {
   using T = typename Payload<EB>::T;
   constexpr uint32_t kThreads = 64u * WAVES;
   const uint32_t lane = threadIdx.x & 63u;
@@ -505,7 +508,7 @@ __device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTi
   if (wave == 0) {
     uint64_t ex;
     if constexpr (LOOKBACK)
-      ex = lookback_exclusive_prefix(status, t.status_first, t.status_idx, tag, uint64_t(total), &hdr->error);
+      ex = lookback_exclusive_prefix(status, t.status_first, t.status_idx, tag, uint64_t(total), &hdr->error, wd);
     else
       ex = tile_prefix[t.status_idx];  // written by an earlier scan pass
     if (lane == 0) lds.t.tile_exclusive = ex;
@@ -553,10 +556,11 @@ __global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shu
   while (tile < a.num_tiles) {
     if (!PIPE) cipher(tile);
     const CompactView v{a.in, a.out, a.n, 0u, tile};
+    auto next_cipher = [&](uint32_t nx) {
+      if (nx < a.num_tiles) cipher(nx);
+    };
     tile = compact_core<EB, WAVES, ITEMS, PIPE, LOOKBACK, false>(v, c, a.hdr, a.status, a.tile_prefix, tag, nt, lds,
-                                                          [&](uint32_t nx) {
-                                                            if (nx < a.num_tiles) cipher(nx);
-                                                          });
+                                                                 a.wd, next_cipher);
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds.t);
 }
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
       const BatchTile b = batch_tile<EB>(a, tile);
       batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
       const uint64_t prefix =
-          tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
+          tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds, a.wd);
       tile_store(cur, nullptr, b.out, b.n, prefix, nt);
       tile = lds.next_ticket;
     }
@@ -669,7 +673,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
     if (tile < limit) {
       const BatchTile b = batch_tile<EB>(a, tile);
       batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
-      cur_prefix = tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds);
+      cur_prefix =
+          tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds, a.wd);
       cur_out = b.out;
       cur_n = b.n;
     }
@@ -683,7 +688,8 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
       }
       tile_store(cur, nullptr, cur_out, cur_n, cur_prefix, nt);
       if (more) {
-        cur_prefix = tile_scan<WAVES, true, true>(nxt.wave_count, a.status, b.first_tile, next, tag, a.hdr, lds);
+        cur_prefix =
+            tile_scan<WAVES, true, true>(nxt.wave_count, a.status, b.first_tile, next, tag, a.hdr, lds, a.wd);
         cur = nxt;
         cur_out = b.out;
         cur_n = b.n;
@@ -733,13 +739,14 @@ __global__ __launch_bounds__(WAVES * 64, (kBatchCompactMinWaves<EB, ITEMS, PIPE>
     }
     const CompactView v{b.in, b.out, b.n, b.first_tile, tile};
     BatchTile nb;
-    tile = compact_core<EB, WAVES, ITEMS, PIPE, true, true>(v, c, a.hdr, a.status, nullptr, tag, nt, lds,
-                                                      [&](uint32_t nx) {
-                                                        if (nx < limit) {
-                                                          nb = batch_tile<EB>(a, nx);
-                                                          cipher(nb);
-                                                        }
-                                                      });
+    auto next_cipher = [&](uint32_t nx) {
+      if (nx < limit) {
+        nb = batch_tile<EB>(a, nx);
+        cipher(nb);
+      }
+    };
+    tile = compact_core<EB, WAVES, ITEMS, PIPE, true, true>(v, c, a.hdr, a.status, nullptr, tag, nt, lds, a.wd,
+                                                            next_cipher);
     if (PIPE) b = nb;
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds.t);

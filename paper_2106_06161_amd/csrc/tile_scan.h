@@ -31,7 +31,17 @@ constexpr uint32_t kValueBits = 38;
 constexpr uint64_t kValueMask = (uint64_t(1) << kValueBits) - 1;
 constexpr uint64_t kFlagAggregate = uint64_t(1) << kValueBits;
 constexpr uint64_t kFlagPrefix = uint64_t(2) << kValueBits;
-constexpr uint32_t kSpinLimit = 1u << 22;  // ~seconds of polling before giving up
+constexpr uint32_t kSpinLimit = 1u << 22;  // ~seconds of polling before giving up (default)
+
+// Look-back watchdog of a launch: polls before a wait gives up (it then sets
+// the sticky timeout error and treats the nearest tile as a prefix of 0, so
+// the launch still finishes), and a test hook: with stall_first set, the
+// first tile of every shuffle withholds its status word, so the next tile's
+// wait deterministically runs into the limit.
+struct Watchdog {
+  uint32_t spin_limit;
+  uint32_t stall_first;
+};
 
 // Sticky device-side error bits kept in the workspace header.
 constexpr uint32_t kErrTimeout = 1u;
@@ -78,11 +88,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // aggregate, looks back, publishes the inclusive prefix, and returns the
 // exclusive prefix (kept indices before the tile, within its segment).
 __device__ __forceinline__ uint64_t lookback_exclusive_prefix(uint64_t* status, uint32_t first_tile,
-                                                              uint32_t tile, uint32_t tag,
-                                                              uint64_t aggregate, uint32_t* error_word) {
+                                                              uint32_t tile, uint32_t tag, uint64_t aggregate,
+                                                              uint32_t* error_word, Watchdog wd) {
   const uint32_t lane = lane_id();
   if (tile == first_tile) {
-    if (lane == 0) atomic_store_agent(status + tile, status_word(tag, kFlagPrefix, aggregate));
+    if (lane == 0 && !wd.stall_first) atomic_store_agent(status + tile, status_word(tag, kFlagPrefix, aggregate));
     return 0;
   }
   if (lane == 0) atomic_store_agent(status + tile, status_word(tag, kFlagAggregate, aggregate));
@@ -113,7 +123,7 @@ __device__ __forceinline__ uint64_t lookback_exclusive_prefix(uint64_t* status, 
       const uint64_t upto = prefix_mask ? (prefix_mask & (~prefix_mask + 1)) : 0;  // lowest P lane bit
       const uint64_t needed = upto ? ((upto << 1) - 1) : ~uint64_t(0);
       if ((not_ready & needed) == 0) break;
-      if (++spins > kSpinLimit) {
+      if (++spins > wd.spin_limit) {
         if (lane == 0) atomicOr(error_word, kErrTimeout);
         ready_mask = ~uint64_t(0);
         prefix_mask = uint64_t(1);  // give up: treat the nearest tile as a prefix

@@ -225,3 +225,8 @@ def test_tuned_lookup_falls_back_to_nearest_class():
         assert B.bs_query_config(0, 16, 1 << 20) == B.bs_get_config()  # none for this size: default
     finally:
         B.bs_load_tuned_configs(B.TUNED_FILE)
+
+
+def test_watchdog_argument_check():
+    assert B.bs_probe_set_watchdog(100, 2) == B.BS_EINVAL
+    assert B.bs_probe_set_watchdog(0, 0) == B.BS_OK
