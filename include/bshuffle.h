@@ -226,14 +226,16 @@ bs_status bs_clear_tuned_configs(void);
  *
  * bs_autotune -- if cache_path names a table made for the architecture of
  * `device`, loads it; otherwise times every compiled shape and grid choice on
- * `device` for element sizes 4, 8 and 16 (single shuffles with domains of
+ * `device` for every element size (single shuffles with domains of
  * 2^12 .. 2^max_size_bits indices, batched launches with mean segment sizes
  * of 2^8 .. 2^min(20, max_size_bits)), installs the fastest per size class
  * and, when cache_path is not NULL, writes the table there.  max_size_bits 0
- * means 30.  Tuning allocates its own buffers (at most half the free device
+ * means 30.  flags: 0, or BS_AUTOTUNE_VERBOSE for one line on stderr per tuned
+ * size class.  Tuning allocates its own buffers (at most half the free device
  * memory, 40 GiB at most) and a stream, takes minutes at the default sizes,
  * and restores any shape forced with bs_set_config.  BS_ENODEV without a
- * device, BS_EINVAL for a bad device index or an unwritable cache_path.
+ * device, BS_EINVAL for a bad device index, unknown flags or an unwritable
+ * cache_path.
  *
  * bs_load_tuned_configs -- replaces the tuned table with the file's entries
  * (the arch line is not checked).  BS_EINVAL if the file cannot be read or an
@@ -246,7 +248,8 @@ bs_status bs_clear_tuned_configs(void);
  * Format: '#' starts a comment; "arch <name>" and "rounds <r>" lines; one
  * entry per line: kind elem_bytes size_bits waves items depth grid_mult [ms].
  */
-bs_status bs_autotune(int device, const char *cache_path, uint32_t max_size_bits);
+#define BS_AUTOTUNE_VERBOSE 1u
+bs_status bs_autotune(int device, const char *cache_path, uint32_t max_size_bits, uint32_t flags);
 bs_status bs_load_tuned_configs(const char *path);
 bs_status bs_save_tuned_configs(const char *path);
 

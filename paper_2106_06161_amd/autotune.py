@@ -39,11 +39,12 @@ def read_table(path: str = TUNED_FILE) -> list[dict]:
     return entries
 
 
-def tune(path: str = TUNED_FILE, device: int = 0, max_size_bits: int = 0) -> list[dict]:
-    """Tunes on `device` (minutes at the default sizes), installs the table and writes it to `path`."""
+def tune(path: str = TUNED_FILE, device: int = 0, max_size_bits: int = 0, verbose: bool = True) -> list[dict]:
+    """Tunes on `device` (minutes at the default sizes; a progress line per size
+    class on stderr), installs the table and writes it to `path`."""
     if os.path.exists(path):
         os.remove(path)  # otherwise bs_autotune would load it as a cache
-    st = B.bs_autotune(device, path, max_size_bits)
+    st = B.bs_autotune(device, path, max_size_bits, B.AUTOTUNE_VERBOSE if verbose else 0)
     B._check(st, "bs_autotune")
     return read_table(path)
 

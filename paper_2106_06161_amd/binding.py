@@ -55,7 +55,7 @@ _SIGNATURES = {
     "bs_unshuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_lcg_params": (_i32, [_u64, _u64, _vp, _vp]),
     "bs_shuffle_lcg": (_i32, [_vp, _vp, _u64, _u32, _u64, _vp, _sz, _vp]),
-    "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32]),
+    "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32, _u32]),
     "bs_load_tuned_configs": (_i32, [ctypes.c_char_p]),
     "bs_save_tuned_configs": (_i32, [ctypes.c_char_p]),
     "bs_probe_shuffle_two_pass": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
@@ -186,8 +186,11 @@ def bs_unshuffle(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, worksp
                                   workspace_bytes, stream))
 
 
-def bs_autotune(device: int, cache_path: str | None, max_size_bits: int = 0) -> int:
-    return int(lib().bs_autotune(device, cache_path.encode() if cache_path else None, max_size_bits))
+AUTOTUNE_VERBOSE = 1
+
+
+def bs_autotune(device: int, cache_path: str | None, max_size_bits: int = 0, flags: int = 0) -> int:
+    return int(lib().bs_autotune(device, cache_path.encode() if cache_path else None, max_size_bits, flags))
 
 
 def bs_load_tuned_configs(path: str) -> int:

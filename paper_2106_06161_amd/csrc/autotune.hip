@@ -230,7 +230,13 @@ bs_status tune_batched(uint32_t eb, uint32_t bits, uint64_t batch_items, hipStre
   return result;
 }
 
-bs_status tune_device(uint32_t max_bits, std::vector<Entry>* out) {
+void report(const Entry& e, bool verbose) {
+  if (verbose)
+    std::fprintf(stderr, "bs_autotune: kind %u elem_bytes %u size_bits %u -> %u %u %u %u (%.4f ms)\n", e.kind,
+                 e.elem_bytes, e.size_bits, e.cfg.waves, e.cfg.items, e.cfg.depth, e.cfg.grid_mult, e.ms);
+}
+
+bs_status tune_device(uint32_t max_bits, bool verbose, std::vector<Entry>* out) {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BS_EHIP;
   const uint64_t budget = std::min<uint64_t>(free_b / 2, kMaxTuneBytes);
@@ -239,7 +245,7 @@ bs_status tune_device(uint32_t max_bits, std::vector<Entry>* out) {
   if (hipStreamCreate(&s) != hipSuccess) return BS_EHIP;
   bs_status st = BS_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = BS_EHIP;
-  for (uint32_t eb : {4u, 8u, 16u}) {
+  for (uint32_t eb : {1u, 2u, 4u, 8u, 16u}) {
     for (uint32_t bits = kMinSingleBits; st == BS_OK && bits <= std::min(max_bits, kMaxSingleBits); ++bits) {
       if ((uint64_t(2) << bits) * eb > budget) break;
       Entry e;
@@ -248,7 +254,10 @@ bs_status tune_device(uint32_t max_bits, std::vector<Entry>* out) {
         st = BS_OK;
         break;
       }
-      if (st == BS_OK) out->push_back(e);
+      if (st == BS_OK) {
+        report(e, verbose);
+        out->push_back(e);
+      }
     }
     for (uint32_t bits = kMinBatchBits; st == BS_OK && bits <= std::min(max_bits, kMaxBatchBits); ++bits) {
       Entry e;
@@ -257,7 +266,10 @@ bs_status tune_device(uint32_t max_bits, std::vector<Entry>* out) {
         st = BS_OK;
         break;
       }
-      if (st == BS_OK) out->push_back(e);
+      if (st == BS_OK) {
+        report(e, verbose);
+        out->push_back(e);
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -287,7 +299,8 @@ extern "C" bs_status bs_save_tuned_configs(const char* path) {
   return write_table(path, arch, entries) ? BS_OK : BS_EINVAL;
 }
 
-extern "C" bs_status bs_autotune(int device, const char* cache_path, uint32_t max_size_bits) {
+extern "C" bs_status bs_autotune(int device, const char* cache_path, uint32_t max_size_bits, uint32_t flags) {
+  if (flags & ~uint32_t(BS_AUTOTUNE_VERBOSE)) return BS_EINVAL;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return BS_ENODEV;
   if (device < 0 || device >= count) return BS_EINVAL;
@@ -302,7 +315,7 @@ extern "C" bs_status bs_autotune(int device, const char* cache_path, uint32_t ma
   if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return BS_EHIP;
   const bsd::ConfigState saved = bsd::config_state();
   std::vector<Entry> entries;
-  bs_status st = tune_device(max_size_bits ? max_size_bits : kMaxSingleBits, &entries);
+  bs_status st = tune_device(max_size_bits ? max_size_bits : kMaxSingleBits, flags & BS_AUTOTUNE_VERBOSE, &entries);
   bsd::restore_config_state(saved);
   (void)hipSetDevice(prev);
   if (st != BS_OK) return st;

@@ -175,6 +175,7 @@ def test_autotune_without_a_device():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present (the GPU test runs the tuner)")
     assert B.bs_autotune(0, None) == B.BS_ENODEV
+    assert B.bs_autotune(0, None, 0, 2) in (B.BS_EINVAL, B.BS_ENODEV)
 
 
 def test_permutation_and_unshuffle_argument_checks():

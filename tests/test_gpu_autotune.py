@@ -29,8 +29,8 @@ def test_autotune_small_classes(tmp_path):
     assert B.bs_set_config(0, 0, 0, 0) == B.BS_OK
     entries = autotune.read_table(str(path))
     singles = {(e["elem_bytes"], e["size_bits"]) for e in entries if e["kind"] == 0}
-    assert singles == {(eb, b) for eb in (4, 8, 16) for b in (12, 13, 14)}
-    assert sum(e["kind"] == 1 for e in entries) == 3 * 7
+    assert singles == {(eb, b) for eb in (1, 2, 4, 8, 16) for b in (12, 13, 14)}
+    assert sum(e["kind"] == 1 for e in entries) == 5 * 7
     shapes = [tuple(s) for s in autotune.SHAPES + autotune.COMPACT_SHAPES]
     assert all((e["waves"], e["items"], e["depth"]) in shapes for e in entries)
     e = next(e for e in entries if e["kind"] == 0 and e["elem_bytes"] == 4 and e["size_bits"] == 14)
