@@ -331,7 +331,7 @@ bs_status bs_query_config(uint32_t kind, uint32_t elem_bytes, uint64_t items, ui
   std::lock_guard<std::mutex> lock(g_mu);
   const uint32_t bits = kind == 0 ? bs_domain_bits(items) : ceil_log2((items + num_segments - 1) / num_segments);
   bsd::LaunchConfig c = pick_config(kind, elem_bytes, bits);
-  if (kind == 0 && bits > 32) c = {bsd::kWideWaves, bsd::kWideItems, 1, c.grid_mult};
+  if (kind == 0 && bits > 32) c = {bsd::kWideWaves, bsd::kWideItems, bsd::kDepthCompactPipe, c.grid_mult};
   if (kind == 1) c = bsd::batch_config(c);
   *waves = c.waves;
   *items_per_lane = c.items;

@@ -101,8 +101,9 @@ using BatchFn = void (*)(BatchArgs);
   X(4, 16, 2) X(8, 16, 2) X(8, 16, 1) X(16, 16, 1) X(16, 8, 1) X(8, 8, 2) X(4, 16, 1) X(16, 16, 2) X(16, 8, 2)
 // Shapes of the LDS-compacted schedule (single shuffles, k <= 32): (waves, items).
 #define BSD_FOR_EACH_COMPACT_SHAPE(X) X(16, 16) X(8, 16) X(16, 8) X(8, 8) X(4, 16)
-// Shape used when the index space needs 64 bits (k > 32).
-constexpr uint32_t kWideWaves = 8, kWideItems = 16;
+// Shape used when the index space needs 64 bits (k > 32): the pipelined
+// compacted schedule for shuffles, the register schedule for the variants.
+constexpr uint32_t kWideWaves = 16, kWideItems = 8;
 
 // Kernel variants (fixed tile shape 16 waves x 16 items): what a kept index
 // produces (0 gather, 1 index, 2 scatter), and how the tile prefix is found.

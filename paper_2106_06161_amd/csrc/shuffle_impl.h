@@ -441,10 +441,10 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
 //   3. thread t gathers ranks t, t + T, t + 2T, ... (T threads) from in[];
 //   4. wavefront 0 runs the look-back while those loads are in flight;
 //   5. rank p is stored at out[prefix + p].
-template <int WAVES, int ITEMS>
+template <int WAVES, int ITEMS, bool WIDE = false>
 struct CompactLds {
   TileLds<WAVES> t;
-  uint32_t y[64 * WAVES * ITEMS];  // kept images of the tile, in rank order
+  std::conditional_t<WIDE, uint64_t, uint32_t> y[64 * WAVES * ITEMS];  // kept images of the tile, in rank order
 };
 
 // One tile as the compacted schedule sees it.
@@ -462,11 +462,11 @@ struct CompactView {
 // With PIPE, next_cipher(next) runs between the gathers and the stores so its
 // VALU work covers the gathers' latency; it leaves the next tile's images in
 // c.  Returns the next ticket.
-template <int EB, int WAVES, int ITEMS, bool PIPE, bool LOOKBACK, bool XCD, typename NextCipher>
-__device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTile<4, kIndices, ITEMS, false>& c,
+template <int EB, int WAVES, int ITEMS, bool PIPE, bool LOOKBACK, bool XCD, bool WIDE, typename NextCipher>
+__device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTile<4, kIndices, ITEMS, WIDE>& c,
                                                  WorkspaceHeader* hdr, uint64_t* status,
                                                  const uint64_t* tile_prefix, uint32_t tag, bool nt,
-                                                 CompactLds<WAVES, ITEMS>& lds, Watchdog wd,
+                                                 CompactLds<WAVES, ITEMS, WIDE>& lds, Watchdog wd,
                                                  NextCipher&& next_cipher) {
   using T = typename Payload<EB>::T;
   constexpr uint32_t kThreads = 64u * WAVES;
@@ -496,13 +496,16 @@ __device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTi
   // gathers for ranks threadIdx.x + q * kThreads, issued before the look-back;
   // lanes past the last rank re-read the last kept record (no per-lane branch,
   // so the payload registers stay independent values)
+  // (EB == 0: no payload, the cipher, compaction and scan only)
   const uint32_t steps = (total + kThreads - 1) / kThreads;
   T v[ITEMS];
+  if constexpr (EB > 0) {
 #pragma unroll
-  for (int q = 0; q < ITEMS; ++q) {
-    if (uint32_t(q) < steps) {
-      const uint32_t p = min(threadIdx.x + uint32_t(q) * kThreads, total - 1);
-      v[q] = load_record<EB>(t.in, lds.y[p]);
+    for (int q = 0; q < ITEMS; ++q) {
+      if (uint32_t(q) < steps) {
+        const uint32_t p = min(threadIdx.x + uint32_t(q) * kThreads, total - 1);
+        v[q] = load_record<EB>(t.in, lds.y[p]);
+      }
     }
   }
   if (wave == 0) {
@@ -516,16 +519,18 @@ __device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTi
   if constexpr (PIPE) next_cipher(next);
   __syncthreads();
   const uint64_t prefix = lds.t.tile_exclusive;
+  if constexpr (EB > 0) {
 #pragma unroll
-  for (int q = 0; q < ITEMS; ++q) {
-    const uint32_t p = threadIdx.x + uint32_t(q) * kThreads;
-    // ranks are < n by construction; the bound only keeps a timed-out
-    // look-back from writing outside the buffer
-    if (uint32_t(q) < steps && p < total && prefix + p < t.n) {
-      if (nt)
-        store_record<EB, true>(t.out, prefix + p, v[q]);
-      else
-        store_record<EB, false>(t.out, prefix + p, v[q]);
+    for (int q = 0; q < ITEMS; ++q) {
+      const uint32_t p = threadIdx.x + uint32_t(q) * kThreads;
+      // ranks are < n by construction; the bound only keeps a timed-out
+      // look-back from writing outside the buffer
+      if (uint32_t(q) < steps && p < total && prefix + p < t.n) {
+        if (nt)
+          store_record<EB, true>(t.out, prefix + p, v[q]);
+        else
+          store_record<EB, false>(t.out, prefix + p, v[q]);
+      }
     }
   }
   return next;
@@ -535,22 +540,24 @@ __device__ __forceinline__ uint32_t compact_core(const CompactView& t, PendingTi
 // indices per lane and records of at most 4 bytes, two 16-wave workgroups fit
 // on a CU (64 VGPRs), so one can compute while the other waits at a barrier or
 // on the look-back.
-template <int EB, int ITEMS>
-constexpr int kCompactMinWaves = (ITEMS <= 8 && EB <= 4) ? 8 : 1;
+template <int EB, int ITEMS, bool WIDE = false>
+constexpr int kCompactMinWaves = (ITEMS <= 8 && EB <= 4 && !WIDE) ? 8 : 1;
 
-template <int EB, bool ODD, int WAVES, int ITEMS, bool PIPE, int BIJ = kBijPhilox, bool LOOKBACK = true>
-__global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shuffle_compact_kernel(
+// WIDE: domains above 2^32, 64-bit images in LDS.
+template <int EB, bool ODD, int WAVES, int ITEMS, bool PIPE, int BIJ = kBijPhilox, bool LOOKBACK = true,
+          bool WIDE = false>
+__global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS, WIDE>)) void shuffle_compact_kernel(
     const SingleArgs a) {
-  __shared__ CompactLds<WAVES, ITEMS> lds;
+  __shared__ CompactLds<WAVES, ITEMS, WIDE> lds;
   group_begin(a.hdr, lds.t);
   const uint32_t gen = lds.t.gen;
   const uint32_t tag = gen & kTagMask;
   const bool nt = a.nontemporal != 0;
   uint32_t tile = lds.t.ticket;
-  PendingTile<4, kIndices, ITEMS, false> c;
+  PendingTile<4, kIndices, ITEMS, WIDE> c;
   auto cipher = [&](uint32_t t) {
-    tile_gather<4, kIndices, ODD, WAVES, ITEMS, false, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, t,
-                                                           a.table, a.lcg_a, a.lcg_c);
+    tile_gather<4, kIndices, ODD, WAVES, ITEMS, WIDE, BIJ>(c, nullptr, a.n, a.domain, a.cs, a.rounds, a.key, t,
+                                                          a.table, a.lcg_a, a.lcg_c);
   };
   if (PIPE && tile < a.num_tiles) cipher(tile);
   while (tile < a.num_tiles) {
@@ -559,8 +566,8 @@ __global__ __launch_bounds__(WAVES * 64, (kCompactMinWaves<EB, ITEMS>)) void shu
     auto next_cipher = [&](uint32_t nx) {
       if (nx < a.num_tiles) cipher(nx);
     };
-    tile = compact_core<EB, WAVES, ITEMS, PIPE, LOOKBACK, false>(v, c, a.hdr, a.status, a.tile_prefix, tag, nt, lds,
-                                                                 a.wd, next_cipher);
+    tile = compact_core<EB, WAVES, ITEMS, PIPE, LOOKBACK, false, WIDE>(v, c, a.hdr, a.status, a.tile_prefix, tag,
+                                                                       nt, lds, a.wd, next_cipher);
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds.t);
 }
@@ -745,8 +752,8 @@ __global__ __launch_bounds__(WAVES * 64, (kBatchCompactMinWaves<EB, ITEMS, PIPE>
         cipher(nb);
       }
     };
-    tile = compact_core<EB, WAVES, ITEMS, PIPE, true, true>(v, c, a.hdr, a.status, nullptr, tag, nt, lds, a.wd,
-                                                            next_cipher);
+    tile = compact_core<EB, WAVES, ITEMS, PIPE, true, true, false>(v, c, a.hdr, a.status, nullptr, tag, nt, lds,
+                                                                   a.wd, next_cipher);
     if (PIPE) b = nb;
   }
   group_end(a.hdr, a.status, a.capacity, gen, lds.t);
@@ -785,8 +792,8 @@ SingleFn pick_variant_eb(bool odd, bool wide) {
 // (waves, items, depth) are listed once in BSD_FOR_EACH_SHAPE (kernels.h).
 template <int EB, bool ODD, bool WIDE>
 SingleFn pick_single_shape(const LaunchConfig& c) {
-  if constexpr (WIDE) {
-    return &shuffle_single_kernel<EB, ODD, 8, 16, 1, true>;
+  if constexpr (WIDE) {  // one shape: compacted, pipelined, 64-bit images
+    return &shuffle_compact_kernel<EB, ODD, kWideWaves, kWideItems, true, kBijPhilox, true, true>;
   } else {
     if (c.depth == kDepthCompact || c.depth == kDepthCompactPipe) {
       const bool pipe = c.depth == kDepthCompactPipe;

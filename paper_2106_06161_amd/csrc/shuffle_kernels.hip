@@ -161,7 +161,7 @@ hipError_t launch_single(const SingleArgs& a0, uint32_t eb, bool nt, const Launc
                          hipStream_t stream) {
   const bool wide = a0.domain > (uint64_t(1) << 32);
   LaunchConfig cfg = cfg0;
-  if (wide) cfg.waves = kWideWaves, cfg.items = kWideItems, cfg.depth = 1;
+  if (wide) cfg.waves = kWideWaves, cfg.items = kWideItems, cfg.depth = kDepthCompactPipe;
   SingleArgs a = a0;
   a.nontemporal = nt ? 1u : 0u;
   const bool odd = ((a.cs.w + a.cs.r) & 1u) != 0;

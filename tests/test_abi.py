@@ -112,7 +112,7 @@ def test_forced_shape_applies_to_both_call_kinds():
         assert B.bs_query_config(1, 4, 1 << 20, 16) == (16, 8, B.DEPTH_COMPACT, 0)
         assert B.bs_set_config(8, 8, B.DEPTH_COMPACT_PIPE, 1) == B.BS_OK
         assert B.bs_query_config(1, 4, 1 << 20, 16) == (8, 8, B.DEPTH_COMPACT_PIPE, 1)
-        assert B.bs_query_config(0, 4, (1 << 32) + 1) == (8, 16, 1, 1)  # 64-bit index path
+        assert B.bs_query_config(0, 4, (1 << 32) + 1) == (16, 8, B.DEPTH_COMPACT_PIPE, 1)  # 64-bit index path
     finally:
         B.bs_set_config(0, 0, 0, 0)
 

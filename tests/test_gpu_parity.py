@@ -237,3 +237,16 @@ def test_capture_without_a_workspace_is_rejected():
     g.replay()
     torch.cuda.synchronize()
     assert bool((y == 3).all())
+
+
+@pytest.mark.parametrize("cfg", [(16, 16, 8, 0), (16, 8, 9, 0), (16, 16, 1, 0)])
+def test_cipher_scan_probe_under_each_schedule(cfg):
+    """The no-payload probe (cipher, keep flags and scan only) runs with every
+    tile schedule and leaves the workspace clean."""
+    assert B.bs_set_config(*cfg) == B.BS_OK
+    ws = bs.make_workspace(bs.workspace_bytes((1 << 22) + 1), device=DEV)
+    sp = torch.cuda.current_stream().cuda_stream
+    for n in (1, 1000, (1 << 22) + 1):
+        assert B.bs_probe_cipher_scan(n, 3, 24, ws.data_ptr(), ws.numel(), sp) == B.BS_OK
+    torch.cuda.synchronize()
+    assert bs.workspace_error(ws) == B.BS_OK
