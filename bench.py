@@ -20,7 +20,8 @@ Prints ONE JSON line:
   fusion       the fused kernel against the less-fused forms of Sec. 6
                (Bijective0: cipher table, compaction, gather as three passes;
                Bijective1: a separate tile-count and scan pass before the
-               gather) and the LCG bijection in the same fused kernel
+               gather), the LCG bijection in the same fused kernel, and the
+               permutation-output and un-shuffle variants
   small        n = 100,000 uint32, 4 rounds: per-call latency
   large        n = 10^9 uint32 and 2.5e8 records of 16 bytes, 24 rounds
   batched      4,096 independent shuffles in one launch vs 4,096 calls
@@ -301,6 +302,21 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None,
     t = timer.run(lcg, 5)
     res["lcg_fused_ms"] = t * 1e3
     res["lcg_fused_Gelem_s"] = n / t / 1e9
+    # the index-output and inverse variants: the permutation itself (4-byte
+    # indices, coalesced writes) and the un-shuffle (coalesced reads,
+    # scattered writes), which must give back x
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    t = timer.run(lambda: bs.permutation(n, SEED, rounds, out=idx, workspace=ws), 5)
+    res["permutation_ms"] = t * 1e3
+    res["permutation_Gelem_s"] = n / t / 1e9
+    bs.shuffle(x, SEED, rounds, out=ref, workspace=ws)
+    z = torch.empty_like(x)
+    t = timer.run(lambda: bs.unshuffle(ref, SEED, rounds, out=z, workspace=ws), 5)
+    res["unshuffle_ms"] = t * 1e3
+    res["unshuffle_Gelem_s"] = n / t / 1e9
+    if not torch.equal(z, x):
+        raise RuntimeError(f"unshuffle did not invert the shuffle at n={n}")
+    del idx, z
     perm = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
     t = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), n, y.data_ptr(), perm.data_ptr(), n, 4, sp), 5)
     res["gather_index_array_ms"] = t * 1e3
