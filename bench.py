@@ -303,8 +303,9 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None,
     res["lcg_fused_ms"] = t * 1e3
     res["lcg_fused_Gelem_s"] = n / t / 1e9
     # the index-output and inverse variants: the permutation itself (4-byte
-    # indices, coalesced writes) and the un-shuffle (coalesced reads,
-    # scattered writes), which must give back x
+    # indices, coalesced writes) and the un-shuffle in its two forms
+    # (coalesced reads and scattered writes through f; coalesced writes and
+    # gathered reads through f^-1), which must give back x
     idx = torch.empty(n, dtype=torch.int32, device=dev)
     t = timer.run(lambda: bs.permutation(n, SEED, rounds, out=idx, workspace=ws), 5)
     res["permutation_ms"] = t * 1e3
@@ -316,7 +317,15 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None,
     res["unshuffle_Gelem_s"] = n / t / 1e9
     if not torch.equal(z, x):
         raise RuntimeError(f"unshuffle did not invert the shuffle at n={n}")
-    del idx, z
+    # the same inverse in gather form through f^-1 (rank table + gather)
+    inv_scratch = torch.empty(B.bs_unshuffle_inverse_scratch_bytes(n), dtype=torch.uint8, device=dev)
+    z.zero_()
+    t = timer.run(lambda: bs.unshuffle_inverse(ref, SEED, rounds, out=z, scratch=inv_scratch), 5)
+    res["unshuffle_inverse_ms"] = t * 1e3
+    res["unshuffle_inverse_Gelem_s"] = n / t / 1e9
+    if not torch.equal(z, x):
+        raise RuntimeError(f"unshuffle_inverse did not invert the shuffle at n={n}")
+    del idx, z, inv_scratch
     perm = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
     t = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), n, y.data_ptr(), perm.data_ptr(), n, 4, sp), 5)
     res["gather_index_array_ms"] = t * 1e3

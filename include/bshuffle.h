@@ -166,6 +166,28 @@ bs_status bs_unshuffle(const void *in, void *out, uint64_t n, uint32_t elem_byte
                        void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * bs_unshuffle_inverse -- the same result as bs_unshuffle, computed in gather
+ * form through the inverse cipher (Sec. 3.2): for every output position
+ * p < n, i = f^-1(p) is the padded index whose image is p, and
+ * out[p] = in[rank(i)], rank(i) being the number of kept indices below i.
+ * The ranks come from a table built in one pass over the padded domain (a
+ * 32-bit mask of kept flags and a 32-bit count per 32 indices, plus one
+ * 64-bit count and prefix per 8192 indices), kept in `scratch`.  Writes are
+ * coalesced; each output reads one table entry and one record at random.
+ *
+ *   scratch  device memory of at least bs_unshuffle_inverse_scratch_bytes(n)
+ *            bytes (about 2^k / 4 bytes for the domain 2^k), 256-byte aligned,
+ *            overlapping neither in nor out; its contents on entry do not
+ *            matter and are overwritten.  NULL or misaligned: BS_EINVAL; too
+ *            small: BS_ENOMEM.
+ * Other arguments and errors as for bs_unshuffle.  No workspace: there is no
+ * look-back.  bs_unshuffle_inverse_scratch_bytes returns 0 for n > BS_MAX_ITEMS.
+ */
+size_t bs_unshuffle_inverse_scratch_bytes(uint64_t n);
+bs_status bs_unshuffle_inverse(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                               uint32_t rounds, void *scratch, size_t scratch_bytes, void *stream);
+
+/*
  * The linear congruential bijection of Sec. 3.1 as the shuffle's f, for
  * comparison with VariablePhilox (Sec. 5 reports its poor quality: at n = 5
  * its chi-square statistic is in the hundreds of thousands).
@@ -182,6 +204,23 @@ bs_status bs_unshuffle(const void *in, void *out, uint64_t n, uint32_t elem_byte
 bs_status bs_lcg_params(uint64_t n, uint64_t seed, uint64_t *a, uint64_t *c);
 bs_status bs_shuffle_lcg(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed, void *workspace,
                          size_t workspace_bytes, void *stream);
+
+/*
+ * bs_bijection -- the keyed bijection alone, applied elementwise: with
+ * inverse = 0, out[j] = f(in[j]); with inverse = 1, out[j] = f^-1(in[j]),
+ * where f is VariablePhilox on [0, 2^domain_bits) with the round keys of
+ * `seed` (Sec. 3.2: the cipher and the three steps that invert it).  For
+ * domain_bits = bs_domain_bits(n), f is the map that bs_shuffle(n, seed,
+ * rounds) applies to padded indices.  Each in[j] is reduced mod
+ * 2^domain_bits first.  in and out are device arrays of `count` uint64_t,
+ * 8-byte aligned (BS_EELEM otherwise); in == out is allowed, other overlap
+ * is not.  domain_bits in [1, BS_MAX_BIJECTION_BITS], rounds <=
+ * BS_MAX_ROUNDS, inverse 0 or 1 (BS_EINVAL otherwise).  No workspace;
+ * asynchronous on `stream`; count == 0 does nothing.
+ */
+#define BS_MAX_BIJECTION_BITS 40u
+bs_status bs_bijection(const uint64_t *in, uint64_t *out, uint64_t count, uint32_t domain_bits, uint64_t seed,
+                       uint32_t rounds, uint32_t inverse, void *stream);
 
 /*
  * Launch configuration (never changes results).  A tile is waves x 64 x items

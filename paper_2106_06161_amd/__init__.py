@@ -13,6 +13,8 @@ from .binding import (  # noqa: F401
     MAX_ITEMS,
     MAX_ROUNDS,
     BShuffleError,
+    bijection,
+    bs_bijection,
     bs_domain_bits,
     bs_get_config,
     bs_lcg_params,
@@ -29,6 +31,7 @@ from .binding import (  # noqa: F401
     shuffle_batched,
     shuffle_lcg,
     unshuffle,
+    unshuffle_inverse,
     workspace_bytes,
     workspace_error,
 )

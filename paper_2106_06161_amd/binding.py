@@ -55,6 +55,9 @@ _SIGNATURES = {
     "bs_unshuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_lcg_params": (_i32, [_u64, _u64, _vp, _vp]),
     "bs_shuffle_lcg": (_i32, [_vp, _vp, _u64, _u32, _u64, _vp, _sz, _vp]),
+    "bs_bijection": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _u32, _vp]),
+    "bs_unshuffle_inverse_scratch_bytes": (_sz, [_u64]),
+    "bs_unshuffle_inverse": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32, _u32]),
     "bs_load_tuned_configs": (_i32, [ctypes.c_char_p]),
     "bs_save_tuned_configs": (_i32, [ctypes.c_char_p]),
@@ -210,6 +213,19 @@ def bs_lcg_params(n: int, seed: int) -> tuple[int, int]:
 def bs_shuffle_lcg(in_ptr, out_ptr, n, elem_bytes, seed, workspace, workspace_bytes, stream) -> int:
     return int(lib().bs_shuffle_lcg(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), workspace, workspace_bytes,
                                     stream))
+
+
+def bs_bijection(in_ptr, out_ptr, count, domain_bits, seed, rounds, inverse, stream) -> int:
+    return int(lib().bs_bijection(in_ptr, out_ptr, count, domain_bits, seed & (2**64 - 1), rounds, inverse, stream))
+
+
+def bs_unshuffle_inverse_scratch_bytes(n) -> int:
+    return int(lib().bs_unshuffle_inverse_scratch_bytes(n))
+
+
+def bs_unshuffle_inverse(in_ptr, out_ptr, n, elem_bytes, seed, rounds, scratch, scratch_bytes, stream) -> int:
+    return int(lib().bs_unshuffle_inverse(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, scratch,
+                                          scratch_bytes, stream))
 
 
 def bs_probe_shuffle_two_pass(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, workspace_bytes,
@@ -372,6 +388,26 @@ def unshuffle(y, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, workspace=No
     return out
 
 
+def unshuffle_inverse(y, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, scratch=None, stream=None):
+    """Inverse of shuffle(x, seed, rounds) along dim 0, in gather form through f^-1."""
+    import torch
+
+    _require_device(y, "y")
+    if out is None:
+        out = torch.empty_like(y)
+    _require_device(out, "out")
+    n, eb = _records(y)
+    need = bs_unshuffle_inverse_scratch_bytes(n)
+    if scratch is None:
+        scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=y.device)
+    _require_device(scratch, "scratch")
+    with torch.cuda.device(y.device):
+        st = bs_unshuffle_inverse(y.data_ptr(), out.data_ptr(), n, eb, seed, rounds, scratch.data_ptr(),
+                                  scratch.numel() * scratch.element_size(), _stream_ptr(y, stream))
+    _check(st, "bs_unshuffle_inverse")
+    return out
+
+
 def shuffle_lcg(x, seed: int, out=None, workspace=None, stream=None):
     """Shuffle of x along dim 0 with the LCG bijection (Sec. 3.1) in place of VariablePhilox."""
     import torch
@@ -387,6 +423,26 @@ def shuffle_lcg(x, seed: int, out=None, workspace=None, stream=None):
     with torch.cuda.device(x.device):
         st = bs_shuffle_lcg(x.data_ptr(), out.data_ptr(), n, eb, seed, ws_ptr, ws_bytes, _stream_ptr(x, stream))
     _check(st, "bs_shuffle_lcg")
+    return out
+
+
+def bijection(x, domain_bits: int, seed: int, rounds: int = DEFAULT_ROUNDS, inverse: bool = False, out=None,
+              stream=None):
+    """f(x) (or f^-1(x)) elementwise for a device int64/uint64 tensor of values in [0, 2^domain_bits)."""
+    import torch
+
+    _require_device(x, "x")
+    if x.dtype not in (torch.int64, torch.uint64) or not x.is_contiguous():
+        raise ValueError("x must be a contiguous int64 or uint64 tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    _require_device(out, "out")
+    if out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must match x in shape and dtype")
+    with torch.cuda.device(x.device):
+        st = bs_bijection(x.data_ptr(), out.data_ptr(), x.numel(), domain_bits, seed, rounds, int(inverse),
+                          _stream_ptr(x, stream))
+    _check(st, "bs_bijection")
     return out
 
 

@@ -638,3 +638,83 @@ extern "C" bs_status bs_shuffle_lcg(const void* in, void* out, uint64_t n, uint3
   a.out = static_cast<uint8_t*>(out);
   return run_variant(a, bsd::kVarLcg, elem_bytes, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
+
+extern "C" bs_status bs_bijection(const uint64_t* in, uint64_t* out, uint64_t count, uint32_t domain_bits,
+                                  uint64_t seed, uint32_t rounds, uint32_t inverse, void* stream) {
+  if (domain_bits < 1 || domain_bits > BS_MAX_BIJECTION_BITS || rounds > BS_MAX_ROUNDS || inverse > 1)
+    return BS_EINVAL;
+  if (count == 0) return BS_OK;
+  if (!in || !out) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % 8 || reinterpret_cast<uintptr_t>(out) % 8) return BS_EELEM;
+  bsd::BijectionArgs a = {};
+  a.in = in;
+  a.out = out;
+  a.count = count;
+  a.cs.w = domain_bits / 2;
+  a.cs.r = domain_bits - a.cs.w;
+  a.cs.wmask = (1u << a.cs.w) - 1u;
+  a.cs.rmask = (1u << a.cs.r) - 1u;
+  a.rounds = rounds;
+  a.inverse = inverse;
+  uint64_t st = seed;
+  for (uint32_t r = 0; r < rounds; ++r) a.key[r] = uint32_t(splitmix64_step(st)) & a.cs.wmask;
+  a.key[rounds] = 0;
+  const hipError_t e = bsd::launch_bijection(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+// ------------------------------------------------- un-shuffle through f^-1 --
+namespace {
+
+struct InverseLayout {
+  size_t table, tile_counts, tile_prefix, total;  // byte offsets into scratch
+};
+
+InverseLayout inverse_layout(uint64_t n) {
+  const uint64_t domain = uint64_t(1) << bs_domain_bits(n);
+  const uint64_t groups = (domain + bsd::kRankGroup - 1) / bsd::kRankGroup;
+  const uint64_t tiles = (domain + bsd::kRankTile - 1) / bsd::kRankTile;
+  InverseLayout l;
+  l.table = 0;
+  l.tile_counts = align256(groups * 8);
+  l.tile_prefix = l.tile_counts + align256(tiles * 8);
+  l.total = l.tile_prefix + align256(tiles * 8);
+  return l;
+}
+
+}  // namespace
+
+extern "C" size_t bs_unshuffle_inverse_scratch_bytes(uint64_t n) {
+  return n > BS_MAX_ITEMS ? 0 : inverse_layout(n).total;
+}
+
+extern "C" bs_status bs_unshuffle_inverse(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                          uint32_t rounds, void* scratch, size_t scratch_bytes, void* stream) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out || !scratch) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (reinterpret_cast<uintptr_t>(scratch) % 256) return BS_EINVAL;
+  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
+  const InverseLayout l = inverse_layout(n);
+  if (scratch_bytes < l.total) return BS_ENOMEM;
+  bsd::SingleArgs c = {};
+  setup_cipher(c, n, seed, rounds);
+  bsd::InverseArgs a = {};
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  a.n = n;
+  a.domain = c.domain;
+  a.cs = c.cs;
+  a.rounds = rounds;
+  a.num_tiles = uint32_t((a.domain + bsd::kRankTile - 1) / bsd::kRankTile);
+  uint8_t* base = static_cast<uint8_t*>(scratch);
+  a.table = reinterpret_cast<uint64_t*>(base + l.table);
+  a.tile_counts = reinterpret_cast<uint64_t*>(base + l.tile_counts);
+  a.tile_prefix = reinterpret_cast<uint64_t*>(base + l.tile_prefix);
+  std::copy(std::begin(c.key), std::end(c.key), std::begin(a.key));
+  const hipError_t e = bsd::launch_unshuffle_inverse(a, elem_bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}

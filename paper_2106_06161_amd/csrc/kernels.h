@@ -63,6 +63,37 @@ struct BatchArgs {
 
 constexpr uint32_t kXcdMinTilesPerSegment = 4;
 
+// Un-shuffle through f^-1 (gather form): a rank table over the padded domain,
+// then out[p] = in[rank(f^-1(p))] for every p < n.
+constexpr uint32_t kRankGroup = 32;                         // indices per table entry
+constexpr uint32_t kRankThreads = 256;                      // entries per rank tile
+constexpr uint32_t kRankTile = kRankGroup * kRankThreads;  // indices per rank tile
+struct InverseArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t n;
+  uint64_t domain;        // 2^k
+  CipherShape cs;
+  uint32_t rounds;
+  uint32_t num_tiles;     // ceil(domain / kRankTile)
+  uint64_t* table;        // ceil(domain / kRankGroup) entries: kept flags (low word),
+                          // kept indices before the entry within its rank tile (high word)
+  uint64_t* tile_counts;  // kept indices per rank tile
+  uint64_t* tile_prefix;  // exclusive prefix of tile_counts
+  uint32_t key[kMaxRounds + 1];  // round keys masked to the half width, then 0
+};
+
+// The bijection alone, elementwise on 64-bit values (bs_bijection).
+struct BijectionArgs {
+  const uint64_t* in;
+  uint64_t* out;
+  uint64_t count;
+  CipherShape cs;
+  uint32_t rounds;
+  uint32_t inverse;  // 1: apply f^-1
+  uint32_t key[kMaxRounds + 1];  // round keys masked to the half width, then 0
+};
+
 struct LaunchConfig {
   uint32_t waves;      // wavefronts per workgroup
   uint32_t items;      // indices per lane per tile
@@ -86,6 +117,8 @@ hipError_t launch_variant(const SingleArgs& a, uint32_t variant, uint32_t elem_b
 hipError_t launch_tile_counts(const SingleArgs& a, hipStream_t stream);
 hipError_t launch_tile_prefix(const uint64_t* counts, uint64_t* prefix, uint32_t tiles, hipStream_t stream);
 hipError_t launch_cipher_table(const SingleArgs& a, uint32_t* table, hipStream_t stream);
+hipError_t launch_bijection(const BijectionArgs& a, hipStream_t stream);
+hipError_t launch_unshuffle_inverse(const InverseArgs& a, uint32_t elem_bytes, hipStream_t stream);
 
 bool config_supported(const LaunchConfig& cfg);
 // The shape a batched launch runs: cfg when compiled, else the default

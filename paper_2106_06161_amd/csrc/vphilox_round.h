@@ -87,4 +87,43 @@ __device__ __forceinline__ void vp_encrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[I
   }
 }
 
+// The inverse, by the three steps of Sec. 3.2 applied to one round's output
+// (L', R') in the same layout (R holds r bits, for odd k bit w is the extra
+// bit; R must arrive clean, without bits above r):
+//   B      = bits [1, w] of R' (odd k; bit 0 is the old extra bit) or R'
+//   L      = B^-1(B) = M0^-1 * B mod 2^w
+//   R      = (F(L) ^ L') & wmask, the old extra bit back in bit w
+// Only the low w <= 24 bits of M0^-1 * B survive, so one 24-bit multiply
+// (v_mul_u32_u24, full rate) with M0^-1 mod 2^24 gives L; F(L) reuses the
+// forward round's product.  Keys are masked to the half width.
+constexpr uint64_t kM0Inverse = 0xF5F365BD212BDF9Bull;
+static_assert(kM0 * kM0Inverse == 1, "kM0Inverse is the inverse of M0 mod 2^64");
+constexpr uint32_t kM0InvLo24 = static_cast<uint32_t>(kM0Inverse) & 0xFFFFFFu;
+
+template <bool ODD>
+__device__ __forceinline__ void vp_round_inverse(uint32_t& L, uint32_t& R, uint32_t key, uint32_t w,
+                                                 uint32_t wmask24) {
+  const uint32_t B = ODD ? (R >> 1) : R;  // below 2^w: R is clean
+  const uint32_t Lp = __umul24(kM0InvLo24, B) & wmask24;
+  const uint64_t p = uint64_t(kM0Lo) * uint64_t(Lp);
+  uint32_t hi;
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(hi) : "s"(kM0Hi24), "v"(Lp), "v"(uint32_t(p >> 32)));
+  const uint32_t low = (hi ^ key ^ L) & wmask24;
+  R = ODD ? low | ((R & 1u) << w) : low;
+  L = Lp;
+}
+
+// Decrypts ITEMS independent blocks (L < 2^w, R < 2^r), rounds in reverse,
+// interleaved like vp_encrypt.  keys[0..rounds) are masked to the half width.
+template <bool ODD, int ITEMS>
+__device__ __forceinline__ void vp_decrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[ITEMS], const CipherShape& cs,
+                                           uint32_t rounds, const uint32_t* __restrict__ keys) {
+  const uint32_t wmask24 = cs.wmask & 0xFFFFFFu;
+  for (uint32_t rr = rounds; rr-- > 0;) {
+    const uint32_t key = keys[rr];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) vp_round_inverse<ODD>(L[j], R[j], key, cs.w, wmask24);
+  }
+}
+
 }  // namespace bsd

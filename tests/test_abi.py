@@ -206,6 +206,30 @@ def test_lcg_argument_checks():
     assert B.bs_shuffle_lcg(FAKE_IN, FAKE_OUT, B.MAX_ITEMS + 1, 1, 1, None, 0, None) == B.BS_EINVAL
 
 
+def test_bijection_argument_checks():
+    for k, rounds, inv in [(0, 24, 0), (41, 24, 0), (10, 65, 0), (10, 24, 2)]:
+        assert B.bs_bijection(FAKE_IN, FAKE_OUT, 8, k, 1, rounds, inv, None) == B.BS_EINVAL
+    assert B.bs_bijection(None, FAKE_OUT, 8, 10, 1, 24, 0, None) == B.BS_EINVAL
+    assert B.bs_bijection(FAKE_IN + 4, FAKE_OUT, 8, 10, 1, 24, 0, None) == B.BS_EELEM
+    assert B.bs_bijection(None, None, 0, 40, 1, 64, 1, None) == B.BS_OK
+
+
+def test_unshuffle_inverse_argument_checks():
+    need = B.bs_unshuffle_inverse_scratch_bytes(1000)
+    assert need >= (1024 // 32) * 8 and need % 256 == 0
+    assert B.bs_unshuffle_inverse_scratch_bytes(B.MAX_ITEMS + 1) == 0
+    # about 2^k / 4 bytes: one 8-byte entry per 32 indices plus per-tile words
+    assert B.bs_unshuffle_inverse_scratch_bytes(1 << 28) <= (1 << 26) + (1 << 19)
+    S = 1 << 42
+    assert B.bs_unshuffle_inverse(FAKE_IN, FAKE_OUT, 1000, 3, 1, 24, S, need, None) == B.BS_EELEM
+    assert B.bs_unshuffle_inverse(FAKE_IN, FAKE_OUT, 1000, 4, 1, 65, S, need, None) == B.BS_EINVAL
+    assert B.bs_unshuffle_inverse(FAKE_IN, FAKE_OUT, 1000, 4, 1, 24, None, need, None) == B.BS_EINVAL
+    assert B.bs_unshuffle_inverse(FAKE_IN, FAKE_OUT, 1000, 4, 1, 24, S + 16, need, None) == B.BS_EINVAL
+    assert B.bs_unshuffle_inverse(FAKE_IN, FAKE_OUT, 1000, 4, 1, 24, S, need - 1, None) == B.BS_ENOMEM
+    assert B.bs_unshuffle_inverse(FAKE_IN, FAKE_IN, 1000, 4, 1, 24, S, need, None) == B.BS_EALIAS
+    assert B.bs_unshuffle_inverse(None, None, 0, 4, 1, 24, None, 0, None) == B.BS_OK
+
+
 def test_xcd_mode_argument_check():
     assert B.bs_probe_set_xcd_mode(3) == B.BS_EINVAL
     for m in (0, 1, 2):

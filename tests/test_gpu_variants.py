@@ -55,6 +55,42 @@ def test_unshuffle_inverts_shuffle(dtype, width):
         assert np.array_equal(z.cpu().numpy(), want), n
 
 
+@pytest.mark.parametrize("dtype,width", [(np.uint8, 0), (np.uint16, 0), (np.uint32, 0), (np.uint64, 0),
+                                         (np.uint64, 2)])
+@pytest.mark.parametrize("rounds", [24, 3, 0])
+def test_unshuffle_through_inverse_matches_oracle(dtype, width, rounds):
+    """Gather form through f^-1: the oracle's inverse map, sizes spanning
+    several rank tiles (8192 indices) with ragged ends, odd and even k."""
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 5, 16, 17, 1000, 8191, 8193, 70_001, 300_001, 1 << 20):
+        shape = (n,) if width == 0 else (n, width)
+        y_np = rng.integers(0, 250, size=shape).astype(dtype)
+        y = torch.from_numpy(y_np).to(DEV)
+        z = bs.unshuffle_inverse(y, 31 + n, rounds)
+        torch.cuda.synchronize()
+        perm = oracle.shuffle_sources(n, 31 + n, rounds).astype(np.int64)
+        want = np.empty_like(y_np)
+        want[perm] = y_np
+        assert np.array_equal(z.cpu().numpy(), want), n
+
+
+def test_unshuffle_forms_agree_and_scratch_is_reused():
+    n = 2_000_003
+    x = torch.from_numpy(W.uniform_u32(n, seed=5)).to(DEV)
+    y = bs.shuffle(x, 12, 24)
+    scratch = torch.full((B.bs_unshuffle_inverse_scratch_bytes(n),), 0xAB, dtype=torch.uint8, device=DEV)
+    a = bs.unshuffle(y, 12, 24)
+    b = bs.unshuffle_inverse(y, 12, 24, scratch=scratch)
+    # a smaller call on the same (now dirty) scratch
+    small = bs.unshuffle_inverse(y[:1000], 4, 24, scratch=scratch)
+    torch.cuda.synchronize()
+    assert torch.equal(a, x) and torch.equal(b, x)
+    assert torch.equal(small, bs.unshuffle(y[:1000], 4, 24))
+    st = B.bs_unshuffle_inverse(y.data_ptr(), a.data_ptr(), n, 4, 12, 24, scratch.data_ptr(), scratch.numel() - 1,
+                                None)
+    assert st == B.BS_ENOMEM
+
+
 @pytest.mark.parametrize("rounds", [24, 5])
 def test_two_pass_and_unfused_equal_fused(rounds):
     for n in SIZES:
