@@ -228,9 +228,10 @@ bs_status bs_bijection(const uint64_t *in, uint64_t *out, uint64_t count, uint32
  * workgroup with the kept records held in registers; BS_DEPTH_COMPACT, where a
  * tile's kept images are first compacted in LDS and then gathered and stored
  * by all lanes in rank order; or BS_DEPTH_COMPACT_PIPE, the same with the next
- * tile's cipher computed while the current tile's gathers are in flight.  The
- * compacted schedules serve batched launches and single shuffles with k <= 32
- * (larger domains always run the register schedule with 64-bit indices).
+ * tile's cipher computed while the current tile's gathers are in flight.
+ * Single shuffles whose domain needs 64-bit indices (k > 32) always run the
+ * pipelined compacted schedule with 16 waves x 8 items, whatever shape is
+ * configured.
  * Compiled shapes (waves, items, depth): (4,16,2) (8,16,2) (8,16,1)
  * (16,16,1) (16,8,1) (8,8,2) (4,16,1) (16,16,2) (16,8,2), and with either
  * compacted schedule (16,16) (8,16) (16,8) (8,8) (4,16).  grid_mult: 0 = a persistent grid of

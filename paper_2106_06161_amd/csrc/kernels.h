@@ -132,7 +132,8 @@ using BatchFn = void (*)(BatchArgs);
 // Tile shapes that are compiled: (waves per workgroup, indices per lane, depth).
 #define BSD_FOR_EACH_SHAPE(X) \
   X(4, 16, 2) X(8, 16, 2) X(8, 16, 1) X(16, 16, 1) X(16, 8, 1) X(8, 8, 2) X(4, 16, 1) X(16, 16, 2) X(16, 8, 2)
-// Shapes of the LDS-compacted schedule (single shuffles, k <= 32): (waves, items).
+// Shapes of the LDS-compacted schedule (single shuffles with k <= 32, and
+// batched launches): (waves, items).
 #define BSD_FOR_EACH_COMPACT_SHAPE(X) X(16, 16) X(8, 16) X(16, 8) X(8, 8) X(4, 16)
 // Shape used when the index space needs 64 bits (k > 32): the pipelined
 // compacted schedule for shuffles, the register schedule for the variants.

@@ -427,10 +427,11 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
 }
 
 // ------------------------------------------------ LDS-compacted tiles --
-// Second tile schedule (narrow domains, k <= 32).  The register schedule above
-// issues each item step's gathers and stores with only the kept lanes active:
-// when about half the padded indices are rejected, twice as many half-empty
-// memory instructions run as kept records need.  Here the kept images of a
+// Second tile schedule (32-bit images in LDS; WIDE: 64-bit images for domains
+// above 2^32).  The register schedule above issues each item step's gathers
+// and stores with only the kept lanes active: when about half the padded
+// indices are rejected, twice as many half-empty memory instructions run as
+// kept records need.  Here the kept images of a
 // tile are first written to LDS in rank order; the workgroup's threads then
 // gather and store consecutive ranks, so every memory instruction runs with
 // all lanes active and each wavefront's stores cover 64 consecutive records.
