@@ -337,14 +337,42 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None,
 
 def bench_small(torch, bs, dev, timer) -> dict:
     """The small single-shuffle workload: n = 100,000 uint32 arange, seed 42,
-    4 rounds (domain 2^17): launch-bound; per-call time on one stream."""
+    4 rounds (domain 2^17): launch-bound; per-call time on one stream, eager
+    and as 100 calls replayed from one graph."""
     n = 100_000
     x = torch.arange(n, dtype=torch.int32, device=dev)
     y = torch.empty_like(x)
     ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
     t = timer.run(lambda: bs.shuffle(x, 42, 4, out=y, workspace=ws), 200, warm=10)
+    ref = y.clone()
+    # the same call 100 times in one captured graph: the device's own time per
+    # call, without the host's per-call launch path
+    calls = 100
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(calls):
+            bs.shuffle(x, 42, 4, out=y, workspace=ws)
+    torch.cuda.synchronize()
+    y.zero_()
+    t_graph = timer.run(g.replay, 20, warm=3) / calls
+    if not torch.equal(y, ref) or bs.workspace_error(ws) != 0:
+        raise RuntimeError("graph replay of the small shuffle differs from the eager call")
+    # launch floor for comparison: a 16-byte copy kernel, 100 per graph
+    from paper_2106_06161_amd import binding as B
+
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=side):
+        for _ in range(calls):
+            B._check(B.bs_probe_copy(x.data_ptr(), y.data_ptr(), 16, side.cuda_stream), "bs_probe_copy")
+    torch.cuda.synchronize()
+    t_floor = timer.run(g2.replay, 20, warm=3) / calls
+    del g, g2
     return {"workload": "n=100,000 uint32 arange, seed 42, 4 rounds, domain 2^17", "us_per_call": t * 1e6,
-            "Gelem_s": n / t / 1e9}
+            "Gelem_s": n / t / 1e9, "us_per_call_graph": t_graph * 1e6, "Gelem_s_graph": n / t_graph / 1e9,
+            "graph_launch_floor_us": t_floor * 1e6}
 
 
 def bench_large(torch, bs, dev, timer, rounds) -> dict:

@@ -11,10 +11,25 @@ namespace {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Each lane moves kCopyUnroll 16-byte vectors per step, all loads issued
+// before the stores, so every wavefront keeps several reads in flight.
+constexpr int kCopyUnroll = 4;
 __global__ __launch_bounds__(256) void copy16_kernel(const u32x4* __restrict__ in, u32x4* __restrict__ out,
                                                      uint64_t vecs) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < vecs; i += stride) out[i] = in[i];
+  const uint64_t step = uint64_t(gridDim.x) * 256 * kCopyUnroll;
+  for (uint64_t base = uint64_t(blockIdx.x) * 256 * kCopyUnroll + threadIdx.x; base < vecs; base += step) {
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int j = 0; j < kCopyUnroll; ++j) {
+      const uint64_t i = base + uint64_t(j) * 256;
+      if (i < vecs) v[j] = in[i];
+    }
+#pragma unroll
+    for (int j = 0; j < kCopyUnroll; ++j) {
+      const uint64_t i = base + uint64_t(j) * 256;
+      if (i < vecs) out[i] = v[j];
+    }
+  }
 }
 
 __global__ void copy_tail_kernel(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, uint64_t bytes) {
@@ -51,8 +66,8 @@ bs_status bs_probe_copy(const void* in, void* out, uint64_t bytes, void* stream)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return BS_EHIP;
-    const uint64_t want = (vecs + 255) / 256;
-    const uint32_t grid = uint32_t(want < uint64_t(cus) * 16 ? want : uint64_t(cus) * 16);
+    const uint64_t want = (vecs + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll);
+    const uint32_t grid = uint32_t(want < uint64_t(cus) * 8 ? want : uint64_t(cus) * 8);
     hipLaunchKernelGGL(copy16_kernel, dim3(grid), dim3(256), 0, s, static_cast<const u32x4*>(in),
                        static_cast<u32x4*>(out), vecs);
   }

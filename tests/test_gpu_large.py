@@ -48,7 +48,8 @@ def test_16_byte_records():
 
 
 def test_domain_beyond_32_bits():
-    """n = 2^32 + 1 one-byte records: k = 33, 64-bit indices."""
+    """n = 2^32 + 1 one-byte records: k = 33, 64-bit indices (shuffle, and
+    both un-shuffle forms back to the input)."""
     n, seed, rounds = (1 << 32) + 1, 3, 4
     x_np = W.random_bytes(n, seed=3)
     x = torch.from_numpy(x_np).to(DEV)
@@ -62,7 +63,15 @@ def test_domain_beyond_32_bits():
         return h
 
     assert torch.equal(histogram(x), histogram(y))
-    del x
+    # both un-shuffle forms invert it on the 64-bit index path
+    z = bs.unshuffle(y, seed, rounds)
+    torch.cuda.synchronize()
+    assert torch.equal(z, x)
+    z.zero_()
+    z = bs.unshuffle_inverse(y, seed, rounds, out=z)
+    torch.cuda.synchronize()
+    assert torch.equal(z, x)
+    del x, z
     y_np = y.cpu().numpy()
     domain = 1 << oracle.domain_bits(n)
     assert domain == 1 << 33
