@@ -128,10 +128,12 @@ __device__ __forceinline__ uint32_t take_ticket(WorkspaceHeader* hdr, TileLds<WA
 }
 
 // The lane that takes a workgroup's tickets after the first one.  The register
-// schedule takes the next ticket once every wave of the workgroup has counted
-// its keeps (a ticket taken earlier sits unstarted while later tiles of its
-// segment wait on it); the compacted schedule takes it as the tile's
-// compaction starts, which hides the atomic's latency behind the compaction.
+// schedule with one tile in flight takes the next ticket once the current
+// tile's prefix is known, and its latency overlaps the stores (a ticket taken
+// earlier sits unstarted through the look-back wait while later tiles of its
+// segment spin on it); with two tiles in flight, once every wave has counted
+// its keeps; the compacted schedule takes it as the tile's compaction starts,
+// which hides the atomic's latency behind the compaction.
 template <int WAVES>
 __device__ __forceinline__ bool ticket_lane() {
   constexpr uint32_t kTicketWave = WAVES > 1 ? 1u : 0u;
@@ -299,8 +301,9 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, MODE, ITEMS, WIDE>& 
 // of lower waves in the tile.  With LOOKBACK the tile's prefix comes from the
 // decoupled look-back; otherwise from tile_prefix[status_idx] (written by an
 // earlier pass).  Takes the workgroup's next ticket once every wave has
-// counted its keeps.
-template <int WAVES, bool LOOKBACK = true, bool XCD = false>
+// counted its keeps; with LATE_TICKET only after the prefix is known (the
+// caller then needs a barrier before it reads lds.next_ticket).
+template <int WAVES, bool LOOKBACK = true, bool XCD = false, bool LATE_TICKET = false>
 __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* status, uint32_t status_first,
                                               uint32_t status_idx, uint32_t tag, WorkspaceHeader* hdr,
                                               TileLds<WAVES>& lds, Watchdog wd,
@@ -316,7 +319,7 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
     wave_exclusive += (uint32_t(w) < wave) ? c : 0u;
     tile_total += c;
   }
-  if (ticket_lane<WAVES>()) lds.next_ticket = take_ticket<XCD>(hdr, lds);
+  if (!LATE_TICKET && ticket_lane<WAVES>()) lds.next_ticket = take_ticket<XCD>(hdr, lds);
   if (wave == 0) {
     uint64_t ex;
     if constexpr (LOOKBACK)
@@ -326,7 +329,9 @@ __device__ __forceinline__ uint64_t tile_scan(uint32_t wave_count, uint64_t* sta
     if (lane == 0) lds.tile_exclusive = ex;
   }
   __syncthreads();
-  return lds.tile_exclusive + wave_exclusive;
+  const uint64_t base = lds.tile_exclusive + wave_exclusive;
+  if (LATE_TICKET && ticket_lane<WAVES>()) lds.next_ticket = take_ticket<XCD>(hdr, lds);
+  return base;
 }
 
 // Writes the kept items: item j's kept lanes take consecutive ranks
@@ -394,9 +399,10 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
       tile_gather<EB, MODE, ODD, WAVES, ITEMS, WIDE, BIJ>(cur, a.in, a.n, a.domain, a.cs, a.rounds, a.key, tile,
                                                           a.table, a.lcg_a, a.lcg_c);
       const uint64_t prefix =
-          tile_scan<WAVES, LOOKBACK>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.wd,
-                                     a.tile_prefix);
+          tile_scan<WAVES, LOOKBACK, false, true>(cur.wave_count, a.status, 0u, tile, tag, a.hdr, lds, a.wd,
+                                                  a.tile_prefix);
       tile_store(cur, a.in, a.out, a.n, prefix, nt);
+      __syncthreads();  // the next ticket, taken after the prefix, is in LDS
       tile = lds.next_ticket;
     }
   } else {
@@ -669,8 +675,9 @@ __global__ __launch_bounds__(WAVES * 64, (kMinWavesPerSimd<EB, ITEMS, DEPTH>)) v
       const BatchTile b = batch_tile<EB>(a, tile);
       batch_gather<EB, WAVES, ITEMS>(cur, b, a.rounds);
       const uint64_t prefix =
-          tile_scan<WAVES, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds, a.wd);
+          tile_scan<WAVES, true, true, true>(cur.wave_count, a.status, b.first_tile, tile, tag, a.hdr, lds, a.wd);
       tile_store(cur, nullptr, b.out, b.n, prefix, nt);
+      __syncthreads();  // the next ticket, taken after the prefix, is in LDS
       tile = lds.next_ticket;
     }
   } else {
