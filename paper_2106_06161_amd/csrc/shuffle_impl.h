@@ -228,10 +228,11 @@ struct PendingTile {
   uint32_t wave_count;                               // kept indices of this wave (uniform)
 };
 
-template <int EB, int MODE, bool ODD, int WAVES, int ITEMS, bool WIDE, int BIJ = kBijPhilox>
+template <int EB, int MODE, bool ODD, int WAVES, int ITEMS, bool WIDE, int BIJ = kBijPhilox,
+          typename Keys = const uint32_t*>
 __device__ __forceinline__ void tile_gather(PendingTile<EB, MODE, ITEMS, WIDE>& t, const uint8_t* __restrict__ in,
                                             uint64_t n, uint64_t domain, const CipherShape cs, uint32_t rounds,
-                                            const uint32_t* __restrict__ keys, uint64_t tile_in_segment,
+                                            Keys keys, uint64_t tile_in_segment,
                                             const uint32_t* __restrict__ table = nullptr, uint64_t lcg_a = 0,
                                             uint64_t lcg_c = 0) {
   using Idx = std::conditional_t<WIDE, uint64_t, uint32_t>;
@@ -620,30 +621,38 @@ struct BatchTile {
   uint8_t* out;
   uint64_t n;
   uint64_t domain;
-  const uint32_t* keys;
+  ConstKeys keys;  // the segment's masked round keys (batch table in the workspace)
   CipherShape cs;
   uint32_t first_tile;
   uint32_t tile_in_segment;
   bool odd;
 };
 
+// The batch tables (tile -> segment, segment records, keys) are written by
+// the preparation kernels and only read here, so they are read through the
+// constant address space: with a uniform tile index these are scalar loads.
+using ConstSegments = const __attribute__((address_space(4))) SegmentInfo*;
+
 template <int EB>
 __device__ __forceinline__ BatchTile batch_tile(const BatchArgs& a, uint32_t tile) {
   BatchTile b;
-  const uint32_t s = __builtin_amdgcn_readfirstlane(a.tile_segment[tile]);
-  const SegmentInfo si = a.segs[s];
-  const uint32_t k = __builtin_amdgcn_readfirstlane(si.k);
+  tile = __builtin_amdgcn_readfirstlane(tile);
+  const uint32_t s = __builtin_amdgcn_readfirstlane(global_keys(a.tile_segment)[tile]);
+  const ConstSegments seg = (ConstSegments)a.segs + s;
+  const uint64_t first = seg->first;
+  const uint32_t first_tile = seg->first_tile;
+  const uint32_t k = __builtin_amdgcn_readfirstlane(seg->k);
   b.cs.w = k >> 1;
   b.cs.r = k - b.cs.w;
   b.cs.wmask = (1u << b.cs.w) - 1u;
   b.cs.rmask = (1u << b.cs.r) - 1u;
-  b.keys = a.keys + uint64_t(s) * (a.rounds + 1);
-  b.in = a.in + si.first * uint64_t(EB);
-  b.out = a.out + si.first * uint64_t(EB);
-  b.n = si.n;
+  b.keys = global_keys(a.keys + uint64_t(s) * (a.rounds + 1));
+  b.in = a.in + first * uint64_t(EB);
+  b.out = a.out + first * uint64_t(EB);
+  b.n = seg->n;
   b.domain = uint64_t(1) << k;
-  b.first_tile = si.first_tile;
-  b.tile_in_segment = tile - si.first_tile;
+  b.first_tile = first_tile;
+  b.tile_in_segment = tile - first_tile;
   b.odd = (k & 1u) != 0;
   return b;
 }

@@ -68,14 +68,23 @@ __device__ __forceinline__ void vp_round(uint32_t& L, uint32_t& Rk, uint32_t key
   Rk = Rn;
 }
 
+// 32-bit words in global memory that nothing writes while the reading kernel
+// runs (the batch tables: round keys, tile -> segment), seen through the
+// constant address space: uniform loads of them then compile to scalar loads
+// even in kernels that also store to global memory (through a generic pointer
+// the round keys cost one vector load per round and wavefront).  Only for
+// pointers into global memory.
+using ConstKeys = const __attribute__((address_space(4))) uint32_t*;
+__device__ __forceinline__ ConstKeys global_keys(const uint32_t* p) { return (ConstKeys)p; }
+
 // Encrypts ITEMS independent blocks, interleaved round by round so that the
 // ITEMS dependency chains fill the VALU pipeline.  keys[0..rounds] are the
 // round keys masked to the half width followed by a 0; they are read one per
-// round from uniform memory (scalar loads), which keeps them out of the
-// scalar register file.
-template <bool ODD, int ITEMS>
+// round from uniform memory (scalar loads: kernel arguments, or ConstKeys),
+// which keeps them out of the scalar register file.
+template <bool ODD, int ITEMS, typename Keys>
 __device__ __forceinline__ void vp_encrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[ITEMS], const CipherShape& cs,
-                                           uint32_t rounds, const uint32_t* __restrict__ keys) {
+                                           uint32_t rounds, Keys keys) {
   const uint32_t wmask24 = cs.wmask & 0xFFFFFFu;
   const uint32_t key0 = keys[0];
 #pragma unroll

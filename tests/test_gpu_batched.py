@@ -148,6 +148,28 @@ def test_batched_under_graph_replay():
     assert bs.workspace_error(ws) == B.BS_OK
 
 
+def test_back_to_back_batches_rewrite_the_key_table():
+    """Consecutive batched launches on one workspace and stream, no sync in
+    between: each launch's prepare kernel rewrites the per-segment key table
+    that the previous launch's tiles read through scalar loads; every output
+    must follow its own seeds and offsets."""
+    ws = bs.make_workspace(bs.workspace_bytes(300_000, 64), device=DEV)
+    cases, outs = [], []
+    for seed in (21, 22, 23):
+        b = W.batch(64 if seed != 22 else 40, 100, 5_000, seed=seed)
+        x_np = W.arange_u32(b["total"])
+        x = torch.from_numpy(x_np).to(DEV)
+        off = torch.from_numpy(b["offsets"]).to(DEV)
+        sd = torch.from_numpy(b["seeds"].view(np.int64)).to(DEV)
+        outs.append(bs.shuffle_batched(x, off, sd, 24, workspace=ws))
+        cases.append((x_np, b))
+    torch.cuda.synchronize()
+    assert bs.workspace_error(ws) == B.BS_OK
+    for (x_np, b), y in zip(cases, outs):
+        want = oracle.shuffle_batched(x_np, b["offsets"], b["seeds"], 24)
+        assert np.array_equal(y.cpu().numpy(), want)
+
+
 def test_bootstrap_shaped_batch_sampled():
     """4,096 segments, sizes log-uniform in [100, 10^6] (seed 3), uint32
     payload = global index: every output value stays in its segment and the
