@@ -10,9 +10,12 @@ real time:
               by element size into one bs_shuffle_batched launch (their inputs
               sit back to back in a device-resident pool); larger requests get
               a bs_shuffle launch of their own;
-  overlap     launches go round-robin to several HIP streams, so requests that
-              arrive while others run are admitted as memory frees up and
-              their work overlaps on the device;
+  overlap     launches go to several HIP streams (policy "size", the
+              default: small groups on a stream of their own, large
+              requests shortest first on the others, none waiting longer
+              than max_wait; policy "fifo": admission order, round-robin),
+              so requests that arrive while others run are admitted as
+              memory frees up and their work overlaps on the device;
   completion  an event per launch; a request's latency is the time from its
               scheduled arrival to the moment its launch is seen complete.
 
