@@ -255,6 +255,12 @@ __device__ __forceinline__ void tile_gather(PendingTile<EB, MODE, ITEMS, WIDE>& 
   uint32_t wave_count = 0, keep_bits = 0;
 #pragma unroll
   for (int s0 = 0; s0 < ITEMS; s0 += kSub) {
+    // a sub-round wholly past the padded domain (small segments, the last
+    // tile of a short shuffle) has nothing to keep: skip its cipher (the
+    // test is uniform per wavefront, so this is a scalar branch)
+    if (!whole_tile &&
+        uint64_t(tile_base) + uint64_t(wave) * (64u * ITEMS) + uint64_t(s0) * 64u > uint64_t(x_last))
+      continue;
     uint32_t L[kSub], R[kSub];
     uint32_t in_domain = whole_tile ? ~0u : 0u;  // bit j: index of item s0+j is < 2^k
     Idx x = base + Idx(s0 * 64);
