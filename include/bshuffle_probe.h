@@ -77,6 +77,16 @@ bs_status bs_probe_set_watchdog(uint32_t spin_limit, uint32_t stall_first_tile);
  */
 bs_status bs_probe_set_xcd_mode(uint32_t mode);
 
+/*
+ * bs_probe_set_batch_small -- how batched launches treat segments whose
+ * padded domain has at most 2^10 indices (never changes results).  1
+ * (default): one wavefront shuffles each such segment in registers, ranking
+ * with its own ballots (no tile, no scan across wavefronts, no look-back), in
+ * a second kernel after the tiled one.  0: every segment gets tiles.  BS_EINVAL
+ * for other values.  Applies to every later call from every thread.
+ */
+bs_status bs_probe_set_batch_small(uint32_t enable);
+
 /* Selects plain (0) or non-temporal (1) output stores for bs_shuffle. */
 bs_status bs_probe_set_store_mode(uint32_t nontemporal);
 

@@ -69,6 +69,7 @@ _SIGNATURES = {
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
     "bs_probe_set_store_mode": (_i32, [_u32]),
     "bs_probe_set_xcd_mode": (_i32, [_u32]),
+    "bs_probe_set_batch_small": (_i32, [_u32]),
     "bs_probe_set_watchdog": (_i32, [_u32, _u32]),
 }
 
@@ -258,6 +259,10 @@ def bs_probe_cipher_scan(n, seed, rounds, workspace, workspace_bytes, stream) ->
 
 def bs_probe_set_watchdog(spin_limit: int, stall_first_tile: int) -> int:
     return int(lib().bs_probe_set_watchdog(spin_limit, stall_first_tile))
+
+
+def bs_probe_set_batch_small(enable: int) -> int:
+    return int(lib().bs_probe_set_batch_small(enable))
 
 
 def bs_probe_set_xcd_mode(mode: int) -> int:

@@ -60,6 +60,7 @@ bsd::LaunchConfig pick_config(uint32_t kind, uint32_t elem_bytes, uint32_t bits)
 }
 bool g_nontemporal_store = false;
 uint32_t g_xcd_mode = 2;  // batched tile ranges per XCD: 0 off, 1 on, 2 automatic
+bool g_batch_small = true;  // batched: segments of <= 2^kSmallSegmentBits indices to one wavefront each
 // look-back watchdog of later launches (spin limit, stall test hook); atomics
 // so the entry points can read them without the lock
 std::atomic<uint32_t> g_spin_limit{bsd::kSpinLimit};
@@ -106,7 +107,7 @@ uint64_t batch_capacity(uint64_t items, uint32_t segments) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct BatchLayout {
-  size_t status, segs, keys, tile_segment, total;
+  size_t status, segs, keys, tile_segment, block_sums, block_bad, total;
   uint64_t capacity;
 };
 
@@ -117,7 +118,10 @@ BatchLayout batch_layout(uint64_t items, uint32_t segments) {
   l.segs = align256(l.status + l.capacity * 8);
   l.keys = align256(l.segs + size_t(segments) * sizeof(bsd::SegmentInfo));
   l.tile_segment = align256(l.keys + size_t(segments) * (BS_MAX_ROUNDS + 1) * 4);
-  l.total = align256(l.tile_segment + l.capacity * 4);
+  const size_t blocks = (size_t(segments) + bsd::kSegmentsPerBlock - 1) / bsd::kSegmentsPerBlock;
+  l.block_sums = align256(l.tile_segment + l.capacity * 4);
+  l.block_bad = align256(l.block_sums + blocks * 4);
+  l.total = align256(l.block_bad + blocks * 4);
   return l;
 }
 
@@ -430,11 +434,14 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
   a.nontemporal = g_nontemporal_store ? 1u : 0u;
   a.wd = current_watchdog();
   a.xcd_mode = g_xcd_mode;
+  a.small_bits = g_batch_small ? bsd::kSmallSegmentBits : 0u;
   a.hdr = reinterpret_cast<bsd::WorkspaceHeader*>(base);
   a.status = reinterpret_cast<uint64_t*>(base + lay.status);
   a.segs = reinterpret_cast<bsd::SegmentInfo*>(base + lay.segs);
   a.keys = reinterpret_cast<uint32_t*>(base + lay.keys);
   a.tile_segment = reinterpret_cast<uint32_t*>(base + lay.tile_segment);
+  a.block_sums = reinterpret_cast<uint32_t*>(base + lay.block_sums);
+  a.block_bad = reinterpret_cast<uint32_t*>(base + lay.block_bad);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
@@ -452,6 +459,13 @@ extern "C" bs_status bs_probe_set_xcd_mode(uint32_t mode) {
   if (mode > 2) return BS_EINVAL;
   std::lock_guard<std::mutex> lock(g_mu);
   g_xcd_mode = mode;
+  return BS_OK;
+}
+
+extern "C" bs_status bs_probe_set_batch_small(uint32_t enable) {
+  if (enable > 1) return BS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_batch_small = enable != 0;
   return BS_OK;
 }
 

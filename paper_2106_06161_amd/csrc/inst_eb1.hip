@@ -4,6 +4,7 @@
 namespace bsd {
 SingleFn pick_single_1(bool odd, bool wide, const LaunchConfig& c) { return pick_single_eb<1>(odd, wide, c); }
 BatchFn pick_batch_1(const LaunchConfig& c) { return pick_batch_eb<1>(c); }
+BatchFn pick_batch_small_1() { return pick_batch_small_eb<1>(); }
 SingleFn pick_variant_1(uint32_t variant, bool odd, bool wide) {
   switch (variant) {
     case kVarScatter: return pick_variant_eb<1, kScatter, true, kBijPhilox>(odd, wide);

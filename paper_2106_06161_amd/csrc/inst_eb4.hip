@@ -4,6 +4,7 @@
 namespace bsd {
 SingleFn pick_single_4(bool odd, bool wide, const LaunchConfig& c) { return pick_single_eb<4>(odd, wide, c); }
 BatchFn pick_batch_4(const LaunchConfig& c) { return pick_batch_eb<4>(c); }
+BatchFn pick_batch_small_4() { return pick_batch_small_eb<4>(); }
 SingleFn pick_variant_4(uint32_t variant, bool odd, bool wide) {
   switch (variant) {
     case kVarIndices: return pick_variant_eb<4, kIndices, true, kBijPhilox>(odd, wide);

@@ -4,6 +4,7 @@
 namespace bsd {
 SingleFn pick_single_8(bool odd, bool wide, const LaunchConfig& c) { return pick_single_eb<8>(odd, wide, c); }
 BatchFn pick_batch_8(const LaunchConfig& c) { return pick_batch_eb<8>(c); }
+BatchFn pick_batch_small_8() { return pick_batch_small_eb<8>(); }
 SingleFn pick_variant_8(uint32_t variant, bool odd, bool wide) {
   switch (variant) {
     case kVarIndices: return pick_variant_eb<8, kIndices, true, kBijPhilox>(odd, wide);

@@ -54,14 +54,23 @@ struct BatchArgs {
   Watchdog wd;              // look-back spin limit (and the stall test hook)
   uint32_t xcd_mode;        // tile ranges per XCD: 0 off, 1 on, 2 when segments average
                             // at least kXcdMinTilesPerSegment tiles
+  uint32_t small_bits;      // segments of at most 2^small_bits padded indices go to the
+                            // one-wavefront kernel instead of tiles (0: none)
   WorkspaceHeader* hdr;
   uint64_t* status;
   SegmentInfo* segs;        // num_segments records
   uint32_t* keys;           // num_segments * (rounds + 1): masked keys, then 0
   uint32_t* tile_segment;   // capacity entries: segment owning each tile
+  uint32_t* block_sums;     // per 256 segments: tiles, then their exclusive prefix
+  uint32_t* block_bad;      // per 256 segments: 1 if one of them is malformed
 };
 
 constexpr uint32_t kXcdMinTilesPerSegment = 4;
+constexpr uint32_t kSegmentsPerBlock = 256;  // batch set-up: segments per workgroup
+// Segments whose padded domain fits one wavefront's items (64 lanes x 16)
+// are shuffled by one wavefront each, with no tile, scan or look-back.
+constexpr uint32_t kSmallSegmentItems = 16;
+constexpr uint32_t kSmallSegmentBits = 10;  // 2^10 = 64 x kSmallSegmentItems
 
 // Un-shuffle through f^-1 (gather form): a rank table over the padded domain,
 // then out[p] = in[rank(f^-1(p))] for every p < n.
@@ -153,6 +162,7 @@ constexpr uint32_t kAltTile = 16u * 64u * 16u;
 #define BSD_DECLARE_PICK(EB)                                                    \
   SingleFn pick_single_##EB(bool odd, bool wide, const LaunchConfig& c);        \
   BatchFn pick_batch_##EB(const LaunchConfig& c);                               \
+  BatchFn pick_batch_small_##EB();                                              \
   SingleFn pick_variant_##EB(uint32_t variant, bool odd, bool wide);
 BSD_DECLARE_PICK(0)
 BSD_DECLARE_PICK(1)

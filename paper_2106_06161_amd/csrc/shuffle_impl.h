@@ -841,6 +841,47 @@ SingleFn pick_single_eb(bool odd, bool wide, const LaunchConfig& c) {
   return odd ? pick_single_shape<EB, true, false>(c) : pick_single_shape<EB, false, false>(c);
 }
 
+// Segments whose padded domain is at most 64 x kSmallSegmentItems indices:
+// one wavefront shuffles a whole segment with its items in registers, ranks
+// from the wavefront's ballots alone (Algorithm 1's scan within one
+// wavefront), so there is no tile, no LDS, no barrier and no look-back; a
+// segment costs a few microseconds of latency instead of a workgroup's tile.
+// Workgroups of one wavefront take segments in a fixed stride (no tickets:
+// nothing waits on anything).  A batch the preparation kernel rejected is
+// left untouched.
+template <int EB>
+__global__ __launch_bounds__(64) void shuffle_batched_small_kernel(const BatchArgs a) {
+  if (__hip_atomic_load(&a.hdr->batch_bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const bool nt = a.nontemporal != 0;
+  for (uint32_t s = blockIdx.x; s < a.num_segments; s += gridDim.x) {
+    const ConstSegments seg = (ConstSegments)a.segs + s;
+    const uint64_t n = seg->n;
+    const uint32_t k = __builtin_amdgcn_readfirstlane(seg->k);
+    if (n == 0 || k > a.small_bits) continue;
+    const uint64_t first = seg->first;
+    CipherShape cs;
+    cs.w = k >> 1;
+    cs.r = k - cs.w;
+    cs.wmask = (1u << cs.w) - 1u;
+    cs.rmask = (1u << cs.r) - 1u;
+    const ConstKeys keys = global_keys(a.keys + uint64_t(s) * (a.rounds + 1));
+    const uint8_t* in = a.in + first * uint64_t(EB);
+    uint8_t* out = a.out + first * uint64_t(EB);
+    PendingTile<EB, kGather, kSmallSegmentItems, false> t;
+    if (k & 1u)
+      tile_gather<EB, kGather, true, 1, kSmallSegmentItems, false>(t, in, n, uint64_t(1) << k, cs, a.rounds, keys, 0);
+    else
+      tile_gather<EB, kGather, false, 1, kSmallSegmentItems, false>(t, in, n, uint64_t(1) << k, cs, a.rounds, keys,
+                                                                    0);
+    tile_store(t, nullptr, out, n, 0, nt);
+  }
+}
+
+template <int EB>
+BatchFn pick_batch_small_eb() {
+  return &shuffle_batched_small_kernel<EB>;
+}
+
 template <int EB>
 BatchFn pick_batch_eb(const LaunchConfig& c) {
   if (c.depth == kDepthCompact || c.depth == kDepthCompactPipe) {

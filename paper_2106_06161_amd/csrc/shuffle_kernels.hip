@@ -8,74 +8,118 @@
 
 namespace bsd {
 
-// One workgroup of 1024 threads: per-segment sizes, domain bits, round keys,
-// and the exclusive scan of tile counts.  Rejects the whole batch (no tile is
-// run) if the offsets are malformed (offsets[0] != 0, decreasing, or past
-// total_items), a segment needs more than 32 index bits,
-// or the tiles exceed the workspace.
-constexpr uint32_t kPrepThreads = 1024;
-__global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(const BatchArgs a) {
-  __shared__ uint32_t warp_sums[kPrepThreads / 64];
-  __shared__ uint32_t carry;
+// Batch set-up, first pass (one thread per segment, 256 segments per
+// workgroup): per-segment records, domain bits and masked round keys; the
+// segment's tile count; its tile offset within its workgroup's 256 segments
+// (stored in first_tile for now); the workgroup's tile total and whether any
+// of its segments is malformed (offsets[0] != 0, decreasing, past
+// total_items, or more than 32 index bits).
+__global__ __launch_bounds__(kSegmentsPerBlock) void batch_segments_kernel(const BatchArgs a) {
+  __shared__ uint32_t warp_sums[kSegmentsPerBlock / 64];
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x;
+  const uint32_t s = blockIdx.x * kSegmentsPerBlock + tid;
+  if (tid == 0) bad = (blockIdx.x == 0 && a.offsets[0] != 0) ? 1u : 0u;
+  __syncthreads();
+  uint32_t tiles = 0;
+  if (s < a.num_segments) {
+    const int64_t lo = a.offsets[s], hi = a.offsets[s + 1];
+    if (hi < lo || lo < 0 || uint64_t(hi) > a.total_items) {
+      atomicOr(&bad, 1u);
+    } else {
+      const uint64_t n = uint64_t(hi - lo);
+      const uint32_t k = domain_bits_dev(n);
+      if (k > 32) atomicOr(&bad, 1u);
+      const uint64_t dom = uint64_t(1) << min(k, 40u);
+      // empty segments, and those the one-wavefront kernel takes, get no tile
+      tiles = (n == 0 || k <= a.small_bits) ? 0u
+                                            : uint32_t(min<uint64_t>((dom + a.tile - 1) / a.tile, 0xFFFFFFFFull));
+      a.segs[s].first = uint64_t(lo);
+      a.segs[s].n = n;
+      a.segs[s].k = k;
+      // round keys masked to the half width, then a 0 (see vp_encrypt)
+      const uint32_t wmask = (1u << (k >> 1)) - 1u;
+      uint32_t* keys = a.keys + uint64_t(s) * (a.rounds + 1);
+      uint64_t st = a.seeds[s];
+      for (uint32_t r = 0; r < a.rounds; ++r) keys[r] = uint32_t(splitmix64_next(st)) & wmask;
+      keys[a.rounds] = 0;
+    }
+  }
+  // workgroup exclusive scan of `tiles` (a segment's tiles fit 2^21, 256 of
+  // them fit 32 bits)
+  uint32_t v = tiles;
+  const uint32_t lane = tid & 63u, warp = tid >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, 64);
+    if (lane >= uint32_t(off)) v += t;
+  }
+  if (lane == 63) warp_sums[warp] = v;
+  __syncthreads();
+  uint32_t warp_prefix = 0, block_total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kSegmentsPerBlock / 64; ++w) {
+    warp_prefix += (w < warp) ? warp_sums[w] : 0u;
+    block_total += warp_sums[w];
+  }
+  if (s < a.num_segments) a.segs[s].first_tile = warp_prefix + v - tiles;
+  if (tid == 0) {
+    a.block_sums[blockIdx.x] = block_total;
+    a.block_bad[blockIdx.x] = bad;
+  }
+}
+
+// Batch set-up, second pass (one workgroup): exclusive scan of the
+// workgroups' tile totals, each segment's first tile made global, the batch
+// accepted or rejected (a malformed segment, or more tiles than the
+// workspace holds: then no tile runs and bs_workspace_error reports
+// BS_EDEVICE), and the launch's header fields.
+constexpr uint32_t kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const BatchArgs a) {
+  __shared__ uint64_t warp_sums[kScanThreads / 64];
+  __shared__ uint64_t carry;
+  __shared__ uint32_t bad;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, warp = tid >> 6;
+  const uint32_t blocks = (a.num_segments + kSegmentsPerBlock - 1) / kSegmentsPerBlock;
   if (tid == 0) {
     carry = 0;
-    bad = (a.offsets[0] != 0) ? 1u : 0u;
+    bad = 0;
   }
   __syncthreads();
-  for (uint32_t base = 0; base < a.num_segments; base += kPrepThreads) {
-    const uint32_t s = base + tid;
-    uint32_t tiles = 0;
-    if (s < a.num_segments) {
-      const int64_t lo = a.offsets[s], hi = a.offsets[s + 1];
-      if (hi < lo || lo < 0 || uint64_t(hi) > a.total_items) {
-        atomicOr(&bad, 1u);
-      } else {
-        const uint64_t n = uint64_t(hi - lo);
-        const uint32_t k = domain_bits_dev(n);
-        if (k > 32) atomicOr(&bad, 1u);
-        const uint64_t dom = uint64_t(1) << min(k, 40u);
-        tiles = (n == 0) ? 0u : uint32_t(min<uint64_t>((dom + a.tile - 1) / a.tile, 0xFFFFFFFFull));
-        a.segs[s].first = uint64_t(lo);
-        a.segs[s].n = n;
-        a.segs[s].k = k;
-        // round keys masked to the half width, then a 0 (see vp_encrypt)
-        const uint32_t wmask = (1u << (k >> 1)) - 1u;
-        uint32_t* keys = a.keys + uint64_t(s) * (a.rounds + 1);
-        uint64_t st = a.seeds[s];
-        for (uint32_t r = 0; r < a.rounds; ++r) keys[r] = uint32_t(splitmix64_next(st)) & wmask;
-        keys[a.rounds] = 0;
-      }
-    }
-    // block exclusive scan of `tiles`
-    uint32_t v = tiles;
-    const uint32_t lane = tid & 63u, warp = tid >> 6;
+  for (uint32_t base = 0; base < blocks; base += kScanThreads) {
+    const uint32_t b = base + tid;
+    const uint64_t c = b < blocks ? a.block_sums[b] : 0u;
+    if (b < blocks && a.block_bad[b]) atomicOr(&bad, 1u);
+    uint64_t v = c;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t t = __shfl_up(v, off, 64);
+      const uint64_t t = __shfl_up(v, off, 64);
       if (lane >= uint32_t(off)) v += t;
     }
     if (lane == 63) warp_sums[warp] = v;
     __syncthreads();
-    uint32_t warp_prefix = 0, block_total = 0;
-    for (uint32_t w = 0; w < kPrepThreads / 64; ++w) {
-      const uint32_t c = warp_sums[w];
-      warp_prefix += (w < warp) ? c : 0u;
-      block_total += c;
+    uint64_t before = 0, total = 0;
+    for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+      before += (w < warp) ? warp_sums[w] : 0u;
+      total += warp_sums[w];
     }
-    const uint64_t first = uint64_t(carry) + warp_prefix + v - tiles;
-    if (s < a.num_segments) {
-      a.segs[s].first_tile = uint32_t(min<uint64_t>(first, 0xFFFFFFFFull));
-      if (first + tiles > a.capacity) atomicOr(&bad, 1u);
-    }
+    // the workgroup's exclusive prefix replaces its total (clamped: a batch
+    // that large is rejected below)
+    if (b < blocks) a.block_sums[b] = uint32_t(min<uint64_t>(carry + before + v - c, 0xFFFFFFFFull));
     __syncthreads();
-    if (tid == 0) carry = uint32_t(min<uint64_t>(uint64_t(carry) + block_total, 0xFFFFFFFFull));
+    if (tid == 0) carry += total;
     __syncthreads();
   }
+  if (tid == 0 && carry > a.capacity) bad = 1u;
+  __syncthreads();
+  if (!bad) {
+    for (uint32_t s = tid; s < a.num_segments; s += kScanThreads)
+      a.segs[s].first_tile += a.block_sums[s / kSegmentsPerBlock];
+  }
   if (tid == 0) {
-    const uint32_t total = bad ? 0u : carry;
+    const uint32_t total = bad ? 0u : uint32_t(carry);
     if (bad) atomicOr(&a.hdr->error, kErrBadBatch);
+    a.hdr->batch_bad = bad;  // read by the one-wavefront kernel
     // XCD ranges start as one range (every tile on XCD 0's counter, which all
     // workgroups reach); with ranges on, batch_fill_kernel moves each boundary
     // down to the first segment that starts at or after x/8 of the tiles
@@ -104,7 +148,7 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(const BatchArgs a) {
       const uint32_t prev = (s == 0) ? 0u : a.segs[s - 1].first_tile;
       if (si.first_tile >= p && (s == 0 || prev < p)) atomicMin(&a.hdr->xcd_first[lane], si.first_tile);
     }
-    if (si.n == 0) continue;
+    if (si.n == 0 || si.k <= a.small_bits) continue;  // no tiles
     const uint64_t dom = uint64_t(1) << si.k;
     const uint32_t tiles = uint32_t((dom + a.tile - 1) / a.tile);
     for (uint32_t t = lane; t < tiles; t += 64) a.tile_segment[si.first_tile + t] = s;
@@ -197,8 +241,12 @@ hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& c
     default: return hipErrorInvalidValue;
   }
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(batch_prepare_kernel, dim3(1), dim3(kPrepThreads), 0, stream, a);
+  const uint32_t seg_blocks = (a.num_segments + kSegmentsPerBlock - 1) / kSegmentsPerBlock;
+  hipLaunchKernelGGL(batch_segments_kernel, dim3(seg_blocks), dim3(kSegmentsPerBlock), 0, stream, a);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, a);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t fill_blocks = std::max(1u, std::min(1024u, (a.num_segments + 3u) / 4u));
   hipLaunchKernelGGL(batch_fill_kernel, dim3(fill_blocks), dim3(256), 0, stream, a);
@@ -208,6 +256,21 @@ hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& c
   // exit at their first ticket.
   const uint32_t grid = grid_for(a.capacity, cfg, num_cus, reinterpret_cast<const void*>(fn));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * 64), 0, stream, a);
+  e = hipGetLastError();
+  if (e != hipSuccess || a.small_bits == 0) return e;
+  // segments small enough for one wavefront: up to 32 one-wavefront
+  // workgroups per CU (8 per SIMD), each taking segments in a fixed stride
+  BatchFn small = nullptr;
+  switch (eb) {
+    case 1: small = pick_batch_small_1(); break;
+    case 2: small = pick_batch_small_2(); break;
+    case 4: small = pick_batch_small_4(); break;
+    case 8: small = pick_batch_small_8(); break;
+    case 16: small = pick_batch_small_16(); break;
+    default: return hipErrorInvalidValue;
+  }
+  const uint32_t small_grid = std::max(1u, std::min(a.num_segments, num_cus * 32u));
+  hipLaunchKernelGGL(small, dim3(small_grid), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 

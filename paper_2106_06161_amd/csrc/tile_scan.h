@@ -61,7 +61,8 @@ struct WorkspaceHeader {
   uint32_t batch_tiles;    // batched launches: tiles of the current batch
   uint32_t xcd_ticket[kXcds];     // batched launches: next tile of each XCD's range
   uint32_t xcd_first[kXcds + 1];  // batched launches: XCD x owns tiles [xcd_first[x], xcd_first[x+1])
-  uint32_t pad[41];
+  uint32_t batch_bad;      // batched launches: 1 when the current batch was rejected
+  uint32_t pad[40];
 };
 static_assert(sizeof(WorkspaceHeader) == 256, "header is 256 bytes");
 

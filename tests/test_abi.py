@@ -230,6 +230,12 @@ def test_unshuffle_inverse_argument_checks():
     assert B.bs_unshuffle_inverse(None, None, 0, 4, 1, 24, None, 0, None) == B.BS_OK
 
 
+def test_batch_small_argument_check():
+    assert B.bs_probe_set_batch_small(2) == B.BS_EINVAL
+    for m in (0, 1):
+        assert B.bs_probe_set_batch_small(m) == B.BS_OK
+
+
 def test_xcd_mode_argument_check():
     assert B.bs_probe_set_xcd_mode(3) == B.BS_EINVAL
     for m in (0, 1, 2):

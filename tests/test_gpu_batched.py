@@ -20,9 +20,11 @@ DEV = "cuda:0"
 def _default_config():
     B.bs_set_config(0, 0, 0, 0)
     B.bs_probe_set_xcd_mode(2)
+    B.bs_probe_set_batch_small(1)
     yield
     B.bs_set_config(0, 0, 0, 0)
     B.bs_probe_set_xcd_mode(2)
+    B.bs_probe_set_batch_small(1)
     assert bs.workspace_error() == B.BS_OK
 
 
@@ -54,6 +56,44 @@ def test_edge_sizes_in_one_batch():
     x = W.uniform_u32(int(offsets[-1]), seed=5)
     got = run_batched(x, offsets, seeds, 24)
     assert np.array_equal(got, oracle.shuffle_batched(x, offsets, seeds, 24))
+
+
+SMALL_SIZES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 64, 100, 255, 257, 511, 513, 1000, 1023, 1024,
+               1025, 2048, 0, 1]
+
+
+@pytest.mark.parametrize("small", [1, 0])
+@pytest.mark.parametrize("dtype,width", [(np.uint8, 0), (np.uint16, 0), (np.uint32, 0), (np.uint64, 0),
+                                         (np.uint64, 2)])
+def test_small_segments_one_wavefront_each(small, dtype, width):
+    """Segments of at most 2^10 padded indices (n <= 1024) go to the
+    one-wavefront kernel by default: every size class from 1 to 1024, around
+    the boundary (1025, 2048 take tiles), and empty segments, for every record
+    size; the same bytes with the path switched off."""
+    B.bs_probe_set_batch_small(small)
+    rng = np.random.default_rng(17)
+    sizes = np.array(SMALL_SIZES * 3 + list(rng.integers(1, 1025, size=300)), dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    seeds = rng.integers(0, 2**63, size=len(sizes), dtype=np.int64).view(np.uint64)
+    total = int(offsets[-1])
+    shape = (total,) if width == 0 else (total, width)
+    x = rng.integers(0, 2**31, size=shape).astype(dtype)
+    for rounds in (24, 0, 5):
+        got = run_batched(x, offsets, seeds, rounds)
+        assert np.array_equal(got, oracle.shuffle_batched(x, offsets, seeds, rounds)), rounds
+
+
+def test_many_tiny_segments_like_a_permutation_test():
+    """100,000 segments of n = 5 (the paper's chi-square setting) in one
+    launch: each equals the oracle's shuffle with its own seed."""
+    S, n = 100_000, 5
+    offsets = (np.arange(S + 1, dtype=np.int64) * n)
+    seeds = np.arange(1, S + 1, dtype=np.uint64)
+    x = np.tile(np.arange(n, dtype=np.uint32), S)
+    got = run_batched(x, offsets, seeds, 24).reshape(S, n)
+    want = oracle.permutations(n, seeds[:2000], 24)
+    assert np.array_equal(got[:2000], want.astype(np.uint32))
+    assert np.array_equal(np.sort(got, axis=1), np.tile(np.arange(n, dtype=np.uint32), (S, 1)))
 
 
 def test_batched_equals_single_calls():
@@ -212,7 +252,10 @@ def test_xcd_ranges_cover_whole_segments():
     batch_tiles, xcd_first = int(hdr[5]), hdr[14:23].astype(np.int64)
     waves, items, _, _ = B.bs_query_config(1, 4, total, S)
     tile = 64 * waves * items
-    tiles = [0 if n == 0 else -(-(1 << B.bs_domain_bits(int(n))) // tile) for n in b["sizes"]]
+    # empty segments and those of at most 2^10 padded indices (one wavefront
+    # each) take no tile
+    tiles = [0 if n == 0 or B.bs_domain_bits(int(n)) <= 10 else -(-(1 << B.bs_domain_bits(int(n))) // tile)
+             for n in b["sizes"]]
     starts = np.concatenate([[0], np.cumsum(tiles)])
     assert batch_tiles == starts[-1]
     assert xcd_first[0] == 0 and xcd_first[8] == batch_tiles
