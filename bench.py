@@ -200,6 +200,44 @@ def cpu_std_shuffle(trials: int = 5) -> dict:
                       f"({dt:.3f} s each) pinned to one core of {cpu_model()}"}
 
 
+def bench_batched_small(torch, bs, B, W, np, dev, timer, rounds) -> list:
+    """Batches of many small segments (the statistical tests' shape: 100,000
+    permutations of n = 5, 100 and 1,000, seeds 1..100,000; and 65,536
+    segments of 10..10^4 records, PCG64 seed 4): one wavefront per segment of
+    at most 1,024 records against every segment in a tile (same bytes)."""
+    cases = [(f"100000 x n={n}", np.arange(100_001, dtype=np.int64) * n, np.arange(1, 100_001, dtype=np.uint64))
+             for n in (5, 100, 1000)]
+    b = W.batch(65536, 10, 10_000, seed=4)
+    cases.append(("65536 x [10, 1e4]", b["offsets"], b["seeds"]))
+    out = []
+    for name, offsets, seeds in cases:
+        total, S = int(offsets[-1]), len(offsets) - 1
+        x = torch.arange(total, dtype=torch.int64, device=dev).to(torch.int32)
+        y = torch.empty_like(x)
+        off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(dev)
+        sd = torch.from_numpy(np.ascontiguousarray(seeds, dtype=np.uint64).view(np.int64)).to(dev)
+        ws = bs.make_workspace(bs.workspace_bytes(total, S), device=dev)
+        row = {"workload": name, "records": total}
+        ref = None
+        try:
+            for small, key in ((1, "one_wavefront"), (0, "tiles_only")):
+                B._check(B.bs_probe_set_batch_small(small), "bs_probe_set_batch_small")
+                t = timer.run(lambda: bs.shuffle_batched(x, off, sd, rounds, out=y, workspace=ws), 5)
+                row[key + "_ms"] = t * 1e3
+                if ref is None:
+                    ref = y.clone()
+                elif not torch.equal(y, ref):
+                    raise RuntimeError(f"small-segment paths differ on {name}")
+        finally:
+            B.bs_probe_set_batch_small(1)
+        row["Gelem_s"] = total / row["one_wavefront_ms"] / 1e6
+        if bs.workspace_error(ws) != 0:
+            raise RuntimeError("device-side error in the small-segment batches")
+        out.append(row)
+        del x, y, ws, ref
+    return out
+
+
 def bench_batched(torch, bs, W, np, dev, stream, timer, rounds) -> dict:
     """4,096 independent shuffles: one batched launch (graph replay) against
     4,096 bs_shuffle calls on one stream, eager and captured in one graph."""
@@ -627,6 +665,8 @@ def main() -> int:
     if not args.no_batched:
         log("bench: batched vs per-call (4,096 segments, log-uniform sizes in [100, 10^6], PCG64 seed 3)")
         result["batched"] = bench_batched(torch, bs, W, np, dev, stream, timer, rounds)
+        log("bench: batches of small segments (100,000 permutations of n = 5 / 100 / 1,000; 65,536 segments)")
+        result["batched_small"] = bench_batched_small(torch, bs, B, W, np, dev, timer, rounds)
 
     if not args.no_serving:
         log(f"bench: serving ({args.serve_requests} requests, sizes log-uniform in [10^3, 10^8], "
