@@ -98,6 +98,11 @@ def parse_args():
                    help="profiler run: one copy of known size, then the steps; no extras")
     p.add_argument("--profile-batched", action="store_true",
                    help="profiler run of the batched workload: --steps batched launches, no extras")
+    p.add_argument("--traffic-record", nargs="+", metavar="PATH",
+                   help="CPU only: print the headline kernel's traffic record (the file the roofline's "
+                        "traffic comes from) from rocprofv3 output: KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON "
+                        "[SQ_DIR [TCC_DIR]] (kernel trace, FETCH_SIZE, WRITE_SIZE, the --profile run's JSON line, "
+                        "SQ and TCC counter runs of bench.py --profile)")
     return p.parse_args()
 
 
@@ -130,6 +135,83 @@ def committed_traffic(digest: str, launch: dict):
         return None
     if rec.get("kernel_source_digest") != digest or rec.get("launch") != launch:
         return None
+    return rec
+
+
+def traffic_record(paths: list) -> dict:
+    """The headline kernel's HBM traffic per launch from rocprofv3 CSVs of
+    `bench.py --profile` runs: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for the run's first kernel, a
+    copy of known size; the kernel's average duration from the kernel trace;
+    optional SQ and TCC counters.  The launch shape comes from the profiled
+    run's JSON line."""
+    import csv
+    import glob
+
+    if not 4 <= len(paths) <= 6:
+        raise SystemExit("--traffic-record needs KT_DIR FETCH_DIR WRITE_DIR BENCH_JSON [SQ_DIR [TCC_DIR]]")
+    kt, fetch_dir, write_dir, bench_json = paths[:4]
+    sq = paths[4] if len(paths) > 4 else None
+    tcc = paths[5] if len(paths) > 5 else None
+    copy_bytes = ((N_HEADLINE * 4) // 16) * 16
+
+    def is_main(name):
+        return "shuffle_compact_kernel" in name or "shuffle_single_kernel" in name
+
+    def rows(d, pattern):
+        with open(glob.glob(os.path.join(d, pattern))[0]) as fh:
+            return list(csv.DictReader(fh))
+
+    main_rows = [r for r in rows(kt, "*kernel_stats.csv") if is_main(r["Name"])]
+    if len(main_rows) != 1:
+        raise SystemExit(f"expected one shuffle kernel in the trace, found {[r['Name'] for r in main_rows]}")
+    mr = main_rows[0]
+
+    def counter(d, name):
+        rs = rows(d, "*counter_collection.csv")
+        copy = [float(r["Counter_Value"]) for r in rs if "copy16_kernel" in r["Kernel_Name"] and r["Counter_Name"] == name]
+        kern = [float(r["Counter_Value"]) for r in rs if is_main(r["Kernel_Name"]) and r["Counter_Name"] == name]
+        return copy, kern
+
+    fc, fk = counter(fetch_dir, "FETCH_SIZE")
+    wc, wk = counter(write_dir, "WRITE_SIZE")
+    fscale = copy_bytes / (fc[0] * 1024.0)
+    wscale = copy_bytes / (wc[0] * 1024.0)
+    fetch = sum(fk) / len(fk) * 1024.0 * fscale
+    write = sum(wk) / len(wk) * 1024.0 * wscale
+    with open(bench_json) as fh:
+        launch = json.loads(fh.read().strip().splitlines()[-1])["config"]["launch"]
+    rec = {
+        "kernel": mr["Name"],
+        "workload": "n=2^27+1 uint32, seed 7, 24 rounds, domain 2^28",
+        "kernel_source_digest": kernel_source_digest(),
+        "fetch_bytes_per_launch": fetch,
+        "write_bytes_per_launch": write,
+        "hbm_bytes_per_launch": fetch + write,
+        "fetch_scale_from_copy": fscale,
+        "write_scale_from_copy": wscale,
+        "copy_probe_bytes": copy_bytes,
+        "copy_fetch_kib": fc[0],
+        "copy_write_kib": wc[0],
+        "kernel_fetch_kib_avg": sum(fk) / len(fk),
+        "kernel_write_kib_avg": sum(wk) / len(wk),
+        "kernel_avg_ms_rocprof": float(mr["AverageNs"]) / 1e6,
+        "kernel_calls_rocprof": int(mr["Calls"]),
+        "launch": launch,
+    }
+    if sq:
+        for name in ("SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+                     "SQ_WAVES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"):
+            _, v = counter(sq, name)
+            if v:
+                rec[name.lower() + "_per_launch"] = sum(v) / len(v)
+    if tcc:
+        for name in ("TCC_EA0_RDREQ_sum", "TCC_EA0_WRREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum"):
+            c, v = counter(tcc, name)
+            if v:
+                rec[name.lower() + "_per_launch"] = sum(v) / len(v)
+            if c:
+                rec[name.lower() + "_copy"] = c[0]
     return rec
 
 
@@ -490,6 +572,9 @@ def bench_serving(rounds: int, count: int) -> dict:
 
 def main() -> int:
     args = parse_args()
+    if args.traffic_record:
+        print(json.dumps(traffic_record(args.traffic_record), indent=1))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the shuffle runs on a single device)", flush=True)
