@@ -69,8 +69,8 @@ def kernel_label(launch: dict) -> str:
     """The fused kernel that runs the headline step (even k, 32-bit indices)."""
     if launch["depth"] in (8, 9):  # kept images compacted through LDS (9: pipelined cipher)
         pipe = "true" if launch["depth"] == 9 else "false"
-        return "bsd::shuffle_compact_kernel<4, false, {waves}, {items}, ".format(**launch) + pipe + ", 0, true>"
-    return "bsd::shuffle_single_kernel<4, false, {waves}, {items}, {depth}, false>".format(**launch)
+        return "bsd::shuffle_compact_kernel<4, false, {waves}, {items}, ".format(**launch) + pipe + ", 0, true, false>"
+    return "bsd::shuffle_single_kernel<4, false, {waves}, {items}, {depth}, false, 0, true, 0>".format(**launch)
 
 
 def log(msg: str) -> None:
