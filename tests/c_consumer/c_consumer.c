@@ -1,8 +1,8 @@
 /*
  * A plain C11 program that uses libbshuffle through its C ABI only (no
  * Python, no torch): device memory from the HIP runtime, bs_shuffle and
- * bs_shuffle_batched on the default stream, a caller-owned workspace, and the
- * error paths.  Results are checked against the sequential oracle
+ * bs_shuffle_batched on the default stream, a caller-owned workspace, the
+ * inverse through f^-1 and the bijection alone, and the error paths.  Results are checked against the sequential oracle
  * (test infrastructure, linked from oracle/liboracle.so).  Prints
  * "c_consumer: OK" and exits 0 on success.
  */
@@ -82,6 +82,38 @@ int main(void) {
     fprintf(stderr, "bs_shuffle_batched differs from the oracle\n");
     return 1;
   }
+
+  /* the inverse: gather form through f^-1 with caller scratch gives the input back */
+  CHECK_BS(bs_shuffle(d_in, d_out, n, 4, 77, rounds, NULL, 0, NULL));
+  void *d_back = NULL, *scratch = NULL;
+  const size_t scratch_bytes = bs_unshuffle_inverse_scratch_bytes(n);
+  CHECK_HIP(hipMalloc(&d_back, n * 4));
+  CHECK_HIP(hipMalloc(&scratch, scratch_bytes));
+  CHECK_BS(bs_unshuffle_inverse(d_out, d_back, n, 4, 77, rounds, scratch, scratch_bytes, NULL));
+  CHECK_HIP(hipDeviceSynchronize());
+  CHECK_HIP(hipMemcpy(h_out, d_back, n * 4, hipMemcpyDeviceToHost));
+  if (memcmp(h_out, h_in, n * 4) != 0) {
+    fprintf(stderr, "bs_unshuffle_inverse did not give the input back\n");
+    return 1;
+  }
+
+  /* the bijection alone: f then f^-1 is the identity on [0, 2^21) */
+  enum { kVals = 4096 };
+  uint64_t vals[kVals], back[kVals];
+  for (int i = 0; i < kVals; ++i) vals[i] = ((uint64_t)i * 2654435761u) & ((1u << 21) - 1);
+  void *d_vals = NULL;
+  CHECK_HIP(hipMalloc(&d_vals, sizeof vals));
+  CHECK_HIP(hipMemcpy(d_vals, vals, sizeof vals, hipMemcpyHostToDevice));
+  CHECK_BS(bs_bijection(d_vals, d_vals, kVals, 21, 99, rounds, 0, NULL));
+  CHECK_BS(bs_bijection(d_vals, d_vals, kVals, 21, 99, rounds, 1, NULL));
+  CHECK_HIP(hipMemcpy(back, d_vals, sizeof back, hipMemcpyDeviceToHost));
+  if (memcmp(back, vals, sizeof vals) != 0) {
+    fprintf(stderr, "bs_bijection inverse did not undo the forward map\n");
+    return 1;
+  }
+  CHECK_HIP(hipFree(d_vals));
+  CHECK_HIP(hipFree(scratch));
+  CHECK_HIP(hipFree(d_back));
 
   /* error paths are reported synchronously, nothing is launched */
   if (bs_shuffle(d_in, d_in, n, 4, 1, rounds, NULL, 0, NULL) != BS_EALIAS ||
