@@ -1,7 +1,8 @@
 """Full-size single shuffles: 10^9 uint32 records, 2.5*10^8 records of 16
-bytes, and a domain past 2^32 (64-bit index path).  Checked on oracle slices
-at the start, middle and end of the padded domain, and by properties that
-hold at any size (the output is a permutation of the input)."""
+bytes, and a domain past 2^32 (64-bit index path, with the un-shuffle forms
+and the LCG bijection).  Checked on oracle slices at the start, middle and end
+of the padded domain, and by properties that hold at any size (the output is a
+permutation of the input)."""
 import numpy as np
 import pytest
 import torch
@@ -76,3 +77,44 @@ def test_domain_beyond_32_bits():
     domain = 1 << oracle.domain_bits(n)
     assert domain == 1 << 33
     check_slices(x_np, y_np, seed, rounds, [0, domain - (1 << 20)])
+
+
+def _lcg_ends(x_np, n, seed, count):
+    """The first and last `count` outputs of Algorithm 1 with the LCG bijection
+    (oracle parameters), walking the padded domain from each end: the kept
+    indices in order give consecutive output slots."""
+    a, c = oracle.lcg_params(n, seed)
+    domain = 1 << oracle.domain_bits(n)
+    head, i = [], 0
+    while len(head) < count:
+        y = (a * i + c) % domain
+        if y < n:
+            head.append(x_np[y])
+        i += 1
+    tail, i = [], domain - 1
+    while len(tail) < count:
+        y = (a * i + c) % domain
+        if y < n:
+            tail.append(x_np[y])
+        i -= 1
+    return np.array(head), np.array(tail[::-1])
+
+
+def test_lcg_beyond_32_bits():
+    """The LCG form on the 64-bit index path (k = 33): a permutation of the
+    input whose first and last 4,096 outputs follow Algorithm 1 exactly."""
+    n, seed = (1 << 32) + 1, 21
+    x_np = W.random_bytes(n, seed=21)
+    x = torch.from_numpy(x_np).to(DEV)
+    y = bs.shuffle_lcg(x, seed)
+    torch.cuda.synchronize()
+    assert bs.workspace_error() == 0
+    hx = torch.zeros(256, dtype=torch.int64, device=DEV)
+    hy = torch.zeros(256, dtype=torch.int64, device=DEV)
+    for cx, cy in zip(torch.split(x, 1 << 28), torch.split(y, 1 << 28)):
+        hx += torch.bincount(cx.to(torch.int32), minlength=256)
+        hy += torch.bincount(cy.to(torch.int32), minlength=256)
+    assert torch.equal(hx, hy)
+    head, tail = _lcg_ends(x_np, n, seed, 4096)
+    assert np.array_equal(y[:4096].cpu().numpy(), head)
+    assert np.array_equal(y[-4096:].cpu().numpy(), tail)
