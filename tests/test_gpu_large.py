@@ -1,6 +1,6 @@
 """Full-size single shuffles: 10^9 uint32 records, 2.5*10^8 records of 16
-bytes, and a domain past 2^32 (64-bit index path, with the un-shuffle forms
-and the LCG bijection).  Checked on oracle slices at the start, middle and end
+bytes, and a domain past 2^32 (64-bit index path, with the un-shuffle forms,
+the index output and the LCG bijection).  Checked on oracle slices at the start, middle and end
 of the padded domain, and by properties that hold at any size (the output is a
 permutation of the input)."""
 import numpy as np
@@ -118,3 +118,42 @@ def test_lcg_beyond_32_bits():
     head, tail = _lcg_ends(x_np, n, seed, 4096)
     assert np.array_equal(y[:4096].cpu().numpy(), head)
     assert np.array_equal(y[-4096:].cpu().numpy(), tail)
+
+
+def test_permutation_beyond_32_bits():
+    """bs_permutation on the 64-bit index path (k = 33, 8-byte indices): its
+    first and last 4,096 entries are the kept images of the padded indices
+    walked from each end (oracle cipher), and all n entries sum and xor to
+    the values of 0 .. n-1."""
+    n, seed, rounds = (1 << 32) + 1, 8, 4
+    idx = bs.permutation(n, seed, rounds, index_dtype=torch.int64, device=DEV)
+    torch.cuda.synchronize()
+    assert bs.workspace_error() == 0
+    c = oracle.Cipher(oracle.domain_bits(n), seed, rounds)
+    head, i = [], 0
+    while len(head) < 4096:
+        y = c.encrypt(i)
+        if y < n:
+            head.append(y)
+        i += 1
+    tail, i = [], (1 << oracle.domain_bits(n)) - 1
+    while len(tail) < 4096:
+        y = c.encrypt(i)
+        if y < n:
+            tail.append(y)
+        i -= 1
+    assert idx[:4096].cpu().tolist() == head
+    assert idx[-4096:].cpu().tolist() == tail[::-1]
+    total, xor = 0, 0
+    for chunk in torch.split(idx, 1 << 28):
+        assert int(chunk.min()) >= 0 and int(chunk.max()) < n
+        total += int(chunk.sum())
+        x = chunk
+        while x.numel() > 1:  # xor-reduce by halves
+            if x.numel() % 2:
+                x = torch.cat([x, torch.zeros(1, dtype=x.dtype, device=x.device)])
+            x = torch.bitwise_xor(x[: x.numel() // 2], x[x.numel() // 2:])
+        xor ^= int(x[0])
+    assert total == n * (n - 1) // 2
+    want_xor = [n - 1, 1, n, 0][(n - 1) % 4]  # xor of 0 .. n-1
+    assert xor == want_xor
