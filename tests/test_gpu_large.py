@@ -157,3 +157,33 @@ def test_permutation_beyond_32_bits():
     assert total == n * (n - 1) // 2
     want_xor = [n - 1, 1, n, 0][(n - 1) % 4]  # xor of 0 .. n-1
     assert xor == want_xor
+
+
+def test_batch_with_a_32_bit_segment():
+    """A batch whose largest segment needs all 32 index bits (2^31 + 1 one-byte
+    records, domain 2^32) between small segments: the small ones equal the
+    oracle, the large one matches oracle slices at both ends of its domain and
+    is a permutation of its input."""
+    big = (1 << 31) + 1
+    sizes = np.array([5, 1000, big, 3, 70_001], dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    seeds = np.array([11, 12, 13, 14, 15], dtype=np.uint64)
+    total = int(offsets[-1])
+    x_np = W.random_bytes(total, seed=31)
+    x = torch.from_numpy(x_np).to(DEV)
+    off = torch.from_numpy(offsets).to(DEV)
+    sd = torch.from_numpy(seeds.view(np.int64)).to(DEV)
+    rounds = 4
+    y = bs.shuffle_batched(x, off, sd, rounds)
+    torch.cuda.synchronize()
+    assert bs.workspace_error() == 0
+    lo, hi = int(offsets[2]), int(offsets[3])
+    hx = torch.bincount(x[lo:hi].to(torch.int32), minlength=256)
+    hy = torch.bincount(y[lo:hi].to(torch.int32), minlength=256)
+    assert torch.equal(hx, hy)
+    y_np = y.cpu().numpy()
+    for s in (0, 1, 3, 4):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        assert np.array_equal(y_np[a:b], oracle.shuffle(x_np[a:b], int(seeds[s]), rounds)), s
+    assert oracle.domain_bits(big) == 32
+    check_slices(x_np[lo:hi], y_np[lo:hi], int(seeds[2]), rounds, [0, (1 << 32) - (1 << 20)])
