@@ -711,6 +711,14 @@ def main() -> int:
         del perm
         ceil["gather_index_array_ms"] = t * 1e3
         ceil["gather_index_array_Gelem_s"] = N_HEADLINE / t / 1e9
+        # random 4-byte reads over 512 MiB at hashed indices, 16 in flight per lane
+        words = 1 << 27
+        sums = torch.empty(words // 16, dtype=torch.int32, device=dev)
+        t = timer.run(lambda: B._check(B.bs_probe_random_reads(x.data_ptr(), words, sums.data_ptr(), 3, sp),
+                                       "bs_probe_random_reads"), 10)
+        del sums
+        ceil["random_reads_512MiB_ms"] = t * 1e3
+        ceil["random_reads_512MiB_G_s"] = words / t / 1e9
         t = timer.run(lambda: B.bs_probe_cipher_scan(N_HEADLINE, SEED, rounds, ws.data_ptr(), ws.numel(), sp), 10)
         ceil["cipher_scan_only_ms"] = t * 1e3
         t = timer.run(lambda: B.bs_probe_cipher_scan(N_HEADLINE, SEED, 4, ws.data_ptr(), ws.numel(), sp), 10)
@@ -724,6 +732,7 @@ def main() -> int:
         ceil["shuffle_pow2_n2p27_Gelem_s"] = (1 << 27) / tp / 1e9
         ceil["shuffle_pct_of_copy"] = 100.0 * achieved / ceil["copy_GBps"]
         ceil["shuffle_pct_of_gather"] = 100.0 * ceil["gather_index_array_ms"] / (kernel_s * 1e3)
+        ceil["shuffle_pct_of_random_read_rate"] = 100.0 * (N_HEADLINE / kernel_s / 1e9) / ceil["random_reads_512MiB_G_s"]
         result["ceilings"] = ceil
         if bs.workspace_error(ws) != 0:
             log("bench: device-side error in ceilings")

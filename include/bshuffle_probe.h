@@ -21,6 +21,15 @@ extern "C" {
  * in/out 16-byte aligned, non-overlapping. */
 bs_status bs_probe_copy(const void *in, void *out, uint64_t bytes, void *stream);
 
+/* The random-read ceiling: words/16 lanes each read 16 uint32 words of `in`
+ * at hashed indices (hash of lane, read and salt, masked to words - 1), all
+ * in flight at once, and write their sum to out[lane] (coalesced; out holds
+ * words/16 uint32).  words is a power of two in [16, 2^32] (BS_EINVAL
+ * otherwise); in and out 4-byte aligned (BS_EELEM).  Measures how many random
+ * 4-byte reads per second the memory system serves, with almost no other
+ * traffic. */
+bs_status bs_probe_random_reads(const void *in, uint64_t words, void *out, uint32_t salt, void *stream);
+
 /* Random gather with an index array: out[j] = in[idx[j]] for j < n, records
  * of elem_bytes (1,2,4,8,16); idx is a device uint32 array whose entries must
  * be < n_in (checked on the device: an out-of-range index is skipped). */

@@ -66,6 +66,7 @@ _SIGNATURES = {
     "bs_probe_shuffle_unfused": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp, _sz, _vp]),
     "bs_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
+    "bs_probe_random_reads": (_i32, [_vp, _u64, _vp, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
     "bs_probe_set_store_mode": (_i32, [_u32]),
     "bs_probe_set_xcd_mode": (_i32, [_u32]),
@@ -259,6 +260,10 @@ def bs_probe_cipher_scan(n, seed, rounds, workspace, workspace_bytes, stream) ->
 
 def bs_probe_set_watchdog(spin_limit: int, stall_first_tile: int) -> int:
     return int(lib().bs_probe_set_watchdog(spin_limit, stall_first_tile))
+
+
+def bs_probe_random_reads(in_ptr, words, out_ptr, salt, stream) -> int:
+    return int(lib().bs_probe_random_reads(in_ptr, words, out_ptr, salt, stream))
 
 
 def bs_probe_set_batch_small(enable: int) -> int:

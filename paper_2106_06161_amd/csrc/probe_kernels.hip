@@ -47,6 +47,31 @@ __global__ __launch_bounds__(256) void gather_kernel(const T* __restrict__ in, u
   }
 }
 
+// The random-read ceiling: each lane issues kRandomReads independent 4-byte
+// loads at hashed word indices (all in flight at once), then one coalesced
+// store of their sum, so nearly all traffic is random line fills.
+constexpr int kRandomReads = 16;
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+__global__ __launch_bounds__(256) void random_reads_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                           uint32_t mask, uint64_t lanes, uint32_t salt) {
+  const uint64_t t = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= lanes) return;
+  uint32_t v[kRandomReads];
+#pragma unroll
+  for (int k = 0; k < kRandomReads; ++k) v[k] = in[hash32(uint32_t(t) * kRandomReads + k + salt) & mask];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kRandomReads; ++k) sum += v[k];
+  out[t] = sum;
+}
+
 int32_t g_probe_hip_error = 0;
 
 }  // namespace
@@ -76,6 +101,22 @@ bs_status bs_probe_copy(const void* in, void* out, uint64_t bytes, void* stream)
     hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(64), 0, s, static_cast<const uint8_t*>(in) + vecs * 16,
                        static_cast<uint8_t*>(out) + vecs * 16, tail);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_probe_hip_error = int32_t(e);
+    return BS_EHIP;
+  }
+  return BS_OK;
+}
+
+bs_status bs_probe_random_reads(const void* in, uint64_t words, void* out, uint32_t salt, void* stream) {
+  if (!in || !out) return BS_EINVAL;
+  if (words < kRandomReads || words > (uint64_t(1) << 32) || (words & (words - 1)) != 0) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % 4 || reinterpret_cast<uintptr_t>(out) % 4) return BS_EELEM;
+  const uint64_t lanes = words / kRandomReads;
+  hipLaunchKernelGGL(random_reads_kernel, dim3(uint32_t((lanes + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), static_cast<const uint32_t*>(in), static_cast<uint32_t*>(out),
+                     uint32_t(words - 1), lanes, salt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     g_probe_hip_error = int32_t(e);

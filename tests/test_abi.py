@@ -236,6 +236,14 @@ def test_batch_small_argument_check():
         assert B.bs_probe_set_batch_small(m) == B.BS_OK
 
 
+def test_random_reads_probe_argument_checks():
+    assert B.bs_probe_random_reads(None, 1 << 10, FAKE_OUT, 0, None) == B.BS_EINVAL
+    assert B.bs_probe_random_reads(FAKE_IN, 1000, FAKE_OUT, 0, None) == B.BS_EINVAL  # not a power of two
+    assert B.bs_probe_random_reads(FAKE_IN, 8, FAKE_OUT, 0, None) == B.BS_EINVAL  # fewer than 16 words
+    assert B.bs_probe_random_reads(FAKE_IN, (1 << 32) * 2, FAKE_OUT, 0, None) == B.BS_EINVAL
+    assert B.bs_probe_random_reads(FAKE_IN + 2, 1 << 10, FAKE_OUT, 0, None) == B.BS_EELEM
+
+
 def test_xcd_mode_argument_check():
     assert B.bs_probe_set_xcd_mode(3) == B.BS_EINVAL
     for m in (0, 1, 2):
