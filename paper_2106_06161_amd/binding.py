@@ -324,8 +324,8 @@ def shuffle(x, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, workspace=None
     if out is None:
         out = torch.empty_like(x)
     _require_device(out, "out")
-    if out.shape != x.shape or out.dtype != x.dtype:
-        raise ValueError("out must match x in shape and dtype")
+    if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype and device")
     n, eb = _records(x)
     ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
     with torch.cuda.device(x.device):
@@ -350,9 +350,14 @@ def shuffle_batched(x, offsets, seeds, rounds: int = DEFAULT_ROUNDS, out=None, t
     s = seeds.numel()
     if offsets.numel() != s + 1:
         raise ValueError("offsets needs num_segments + 1 entries")
+    for t, name in ((offsets, "offsets"), (seeds, "seeds")):
+        if t.device != x.device:
+            raise ValueError(f"{name} must be on x's device ({x.device}), not {t.device}")
     if out is None:
         out = torch.empty_like(x)
     _require_device(out, "out")
+    if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype and device")
     n, eb = _records(x)
     total = n if total_items is None else int(total_items)
     if total > n:

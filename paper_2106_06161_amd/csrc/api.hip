@@ -442,6 +442,8 @@ bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, 
   a.tile_segment = reinterpret_cast<uint32_t*>(base + lay.tile_segment);
   a.block_sums = reinterpret_cast<uint32_t*>(base + lay.block_sums);
   a.block_bad = reinterpret_cast<uint32_t*>(base + lay.block_bad);
+  a.tables = base + lay.segs;
+  a.tables_bytes = lay.total - lay.segs;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);

@@ -63,6 +63,8 @@ struct BatchArgs {
   uint32_t* tile_segment;   // capacity entries: segment owning each tile
   uint32_t* block_sums;     // per 256 segments: tiles, then their exclusive prefix
   uint32_t* block_bad;      // per 256 segments: 1 if one of them is malformed
+  uint8_t* tables;          // first byte of the tables above (256-byte aligned)
+  uint64_t tables_bytes;    // bytes of all the tables (a multiple of 256), zeroed after the launch
 };
 
 constexpr uint32_t kXcdMinTilesPerSegment = 4;

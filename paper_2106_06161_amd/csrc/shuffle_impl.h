@@ -161,8 +161,13 @@ __device__ __forceinline__ void group_begin(WorkspaceHeader* hdr, TileLds<WAVES>
 }
 
 // Ends a workgroup.  The last one to finish resets the ticket and the done
-// counter and advances the generation; when the 24-bit tag wraps it first
-// clears every status word so no stale word can carry a future tag.
+// counter, raises the workspace's high-water mark of status words to this
+// launch's `capacity`, and advances the generation; when the 24-bit tag wraps
+// it first clears every status word up to that mark, so no stale word can
+// carry a future tag.  Only status words are cleared: the batch tables that
+// follow a batched launch's status words are not touched (the one-wavefront
+// kernel that reads them runs before the tiled kernel, and a separate kernel
+// zeroes them after it).
 // Ordering without fences: a workgroup's last ticket fetch returned its value
 // before the workgroup got here, and the wait below retires its status stores
 // before it counts itself done; the done counter's modification order then
@@ -178,15 +183,16 @@ __device__ __forceinline__ void group_end(WorkspaceHeader* hdr, uint64_t* status
   __syncthreads();
   if (lds.last) {
     const uint32_t next_gen = gen + 1;
+    const uint32_t hwm = max(capacity, hdr->status_hwm);
     if ((next_gen & kTagMask) == 0) {
-      const uint32_t cap = max(capacity, hdr->capacity);
-      for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) atomic_store_agent(status + i, 0);
+      for (uint32_t i = threadIdx.x; i < hwm; i += blockDim.x) atomic_store_agent(status + i, 0);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
     if (threadIdx.x < kXcds)
       __hip_atomic_store(&hdr->xcd_ticket[threadIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) {
+      __hip_atomic_store(&hdr->status_hwm, hwm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&hdr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&hdr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&hdr->gen, next_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

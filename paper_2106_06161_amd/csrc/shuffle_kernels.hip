@@ -155,6 +155,14 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(const BatchArgs a) {
   }
 }
 
+// Zeroes a batched launch's tables once its kernels are done with them (16
+// bytes per store; the region is 256-byte aligned and sized).
+__global__ __launch_bounds__(256) void zero_tables_kernel(uint4* p, uint64_t count16) {
+  const uint4 z = {0u, 0u, 0u, 0u};
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count16; i += uint64_t(gridDim.x) * blockDim.x)
+    p[i] = z;
+}
+
 // Zero-fills a workspace and records its status-word capacity in the header.
 __global__ void zero_fill_kernel(uint32_t* p, uint64_t words, uint32_t capacity_words) {
   constexpr uint64_t kCapacityWord = offsetof(WorkspaceHeader, capacity) / sizeof(uint32_t);
@@ -252,25 +260,38 @@ hipError_t launch_batched(const BatchArgs& a, uint32_t eb, const LaunchConfig& c
   hipLaunchKernelGGL(batch_fill_kernel, dim3(fill_blocks), dim3(256), 0, stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // Segments small enough for one wavefront first: up to 32 one-wavefront
+  // workgroups per CU (8 per SIMD), each taking segments in a fixed stride.
+  // They run before the tiled kernel because that kernel's last workgroup may
+  // clear status words past this launch's own (at a tag wrap), which can
+  // reach the tables.
+  if (a.small_bits != 0) {
+    BatchFn small = nullptr;
+    switch (eb) {
+      case 1: small = pick_batch_small_1(); break;
+      case 2: small = pick_batch_small_2(); break;
+      case 4: small = pick_batch_small_4(); break;
+      case 8: small = pick_batch_small_8(); break;
+      case 16: small = pick_batch_small_16(); break;
+      default: return hipErrorInvalidValue;
+    }
+    const uint32_t small_grid = std::max(1u, std::min(a.num_segments, num_cus * 32u));
+    hipLaunchKernelGGL(small, dim3(small_grid), dim3(64), 0, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   // The grid never exceeds the workspace's tile capacity; surplus workgroups
   // exit at their first ticket.
   const uint32_t grid = grid_for(a.capacity, cfg, num_cus, reinterpret_cast<const void*>(fn));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.waves * 64), 0, stream, a);
   e = hipGetLastError();
-  if (e != hipSuccess || a.small_bits == 0) return e;
-  // segments small enough for one wavefront: up to 32 one-wavefront
-  // workgroups per CU (8 per SIMD), each taking segments in a fixed stride
-  BatchFn small = nullptr;
-  switch (eb) {
-    case 1: small = pick_batch_small_1(); break;
-    case 2: small = pick_batch_small_2(); break;
-    case 4: small = pick_batch_small_4(); break;
-    case 8: small = pick_batch_small_8(); break;
-    case 16: small = pick_batch_small_16(); break;
-    default: return hipErrorInvalidValue;
-  }
-  const uint32_t small_grid = std::max(1u, std::min(a.num_segments, num_cus * 32u));
-  hipLaunchKernelGGL(small, dim3(small_grid), dim3(64), 0, stream, a);
+  if (e != hipSuccess) return e;
+  // The tables sit where a later launch with more tiles keeps status words:
+  // leave them zero.
+  const uint64_t count16 = a.tables_bytes / 16;
+  const uint32_t zero_blocks = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(1024, (count16 + 255) / 256)));
+  hipLaunchKernelGGL(zero_tables_kernel, dim3(zero_blocks), dim3(256), 0, stream, reinterpret_cast<uint4*>(a.tables),
+                     count16);
   return hipGetLastError();
 }
 

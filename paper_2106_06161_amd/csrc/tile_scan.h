@@ -17,7 +17,12 @@
 //   bits 37..0   value
 // A word whose tag differs from the current launch's is "nothing yet", so the
 // status array never needs clearing between launches; when the 24-bit tag
-// wraps, the launch's last workgroup clears the whole array.
+// wraps, the launch's last workgroup clears every status word any launch on
+// the workspace has used (the header's high-water mark).  The status array
+// must never hold anything but status words or zeros: batched launches keep
+// their tables after their own status words and zero them once the launch is
+// done, so a later launch with a larger status array cannot read stale table
+// bytes as status words.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,12 +62,13 @@ struct WorkspaceHeader {
   uint32_t done;           // workgroups finished in this launch
   uint32_t gen;            // launch generation; its low 24 bits tag status words
   uint32_t error;          // sticky error bits
-  uint32_t capacity;       // status words the workspace holds (set at init)
+  uint32_t capacity;       // status words the workspace holds (set at init; informational)
   uint32_t batch_tiles;    // batched launches: tiles of the current batch
   uint32_t xcd_ticket[kXcds];     // batched launches: next tile of each XCD's range
   uint32_t xcd_first[kXcds + 1];  // batched launches: XCD x owns tiles [xcd_first[x], xcd_first[x+1])
   uint32_t batch_bad;      // batched launches: 1 when the current batch was rejected
-  uint32_t pad[40];
+  uint32_t status_hwm;     // status words used by any launch since init (cleared at a tag wrap)
+  uint32_t pad[39];
 };
 static_assert(sizeof(WorkspaceHeader) == 256, "header is 256 bytes");
 

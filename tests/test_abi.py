@@ -269,3 +269,28 @@ def test_tuned_lookup_falls_back_to_nearest_class():
 def test_watchdog_argument_check():
     assert B.bs_probe_set_watchdog(100, 2) == B.BS_EINVAL
     assert B.bs_probe_set_watchdog(0, 0) == B.BS_OK
+
+
+def test_tensor_wrappers_check_out_and_devices(monkeypatch):
+    """shuffle / shuffle_batched reject an `out` that does not match x (a
+    smaller one would take out-of-bounds device writes) and batch tables on
+    another device, before any pointer reaches the library.  Meta tensors
+    stand in for device tensors (no GPU here)."""
+    import torch
+
+    monkeypatch.setattr(B, "_require_device", lambda t, name: None)
+    x = torch.empty(1000, dtype=torch.int32, device="meta")
+    off = torch.empty(3, dtype=torch.int64, device="meta")
+    sd = torch.empty(2, dtype=torch.int64, device="meta")
+    for bad in (torch.empty(999, dtype=torch.int32, device="meta"),
+                torch.empty(1000, dtype=torch.int64, device="meta"),
+                torch.empty((1000, 2), dtype=torch.int32, device="meta")):
+        with pytest.raises(ValueError, match="out must match"):
+            B.shuffle_batched(x, off, sd, out=bad)
+        with pytest.raises(ValueError, match="out must match"):
+            B.shuffle(x, 1, out=bad)
+    with pytest.raises(ValueError, match="offsets must be on"):
+        B.shuffle_batched(x, torch.zeros(3, dtype=torch.int64), sd)
+    with pytest.raises(ValueError, match="seeds must be on"):
+        B.shuffle_batched(x, off, torch.zeros(2, dtype=torch.int64))
+
