@@ -17,7 +17,13 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vphilox_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 builds and loads a copy instrumented with AddressSanitizer
+# and UndefinedBehaviorSanitizer (any report aborts); the process must preload
+# the ASan runtime (LD_PRELOAD=$(gcc -print-file-name=libasan.so)).
+SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=all"]
 _STD_SRC = os.path.join(_HERE, "std_shuffle.cpp")
 _STD_LIB = os.path.join(_HERE, "libstdshuffle.so")
 
@@ -31,8 +37,9 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
+        opt = _SAN_FLAGS if SANITIZE else ["-O2"]
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp]
+            ["gcc", *opt, "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp]
         )
         os.replace(tmp, _LIB)
     if force or not os.path.exists(_STD_LIB) or os.path.getmtime(_STD_LIB) < os.path.getmtime(_STD_SRC):

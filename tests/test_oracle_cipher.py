@@ -180,3 +180,26 @@ def test_below_four_bits_the_family_is_tiny(k, bound):
         assert len(tabs) <= bound
     tabs4 = {oracle.Cipher(4, s, 24).table().tobytes() for s in range(2000)}
     assert len(tabs4) > 1000
+
+
+@pytest.mark.parametrize("k", [8, 9, 16, 17, 24, 25, 33])
+@pytest.mark.parametrize("rounds", [1, 2, 24])
+def test_round_key_enters_only_the_new_left_half(k, rounds):
+    """Where the key enters a round (reading C4).  The text calls both F_k and
+    B_k key-dependent; the listing keys only the round function: the key is
+    xored into F's output, which lands in L', and B(L) carries no key.  So in
+    the last round, changing that round's key by d (d below the half width)
+    changes L' by exactly d and leaves R' and b' alone.  A key folded into B,
+    or into R', or combined with F by addition, fails this."""
+    w = k // 2
+    rng = np.random.default_rng(1000 * k + rounds)
+    base = oracle.Cipher(k, 4242 + k, rounds)
+    xs = [int(v) for v in rng.integers(0, 1 << k, size=64, dtype=np.uint64)]
+    ys = [base.encrypt(x) for x in xs]
+    for d in [1, (1 << w) - 1] + [int(v) for v in rng.integers(1, 1 << w, size=6)]:
+        alt = oracle.Cipher(k, 4242 + k, rounds)
+        alt._c.key[rounds - 1] ^= d
+        for x, y in zip(xs, ys):
+            Ly, by, Ry = _split(y, k)
+            La, ba, Ra = _split(alt.encrypt(x), k)
+            assert (La ^ Ly, ba, Ra) == (d, by, Ry), (k, rounds, d, x)

@@ -16,6 +16,7 @@ first block at 24 rounds sits at z = +2.29, inside alpha = 0.01 but outside
 import math
 
 import numpy as np
+from scipy import stats as scipy_stats
 import pytest
 
 import oracle
@@ -119,3 +120,70 @@ def test_mmd_n100_pass_at_24_fail_at_4():
     assert abs(m24) < stats.normal_threshold(100, P, 0.01)
     m4 = stats.mmd2(_perms(100, 4))
     assert abs(m4) > stats.normal_threshold(100, P, 0.05)
+
+
+# ------------------------------------------- acceptance bounds (Sec. 5) ----
+# The three acceptance bounds are pinned against the null distribution itself
+# (numpy's uniform permutations, independent of the oracle's cipher) and
+# against library routines that compute the same quantities another way.
+def _null_mmd2(n, sample_size, samples, seed):
+    rng = np.random.default_rng(seed)
+    base = np.tile(np.arange(n, dtype=np.uint32), (sample_size * samples, 1))
+    perms = rng.permuted(base, axis=1).reshape(samples, sample_size, n)
+    return np.array([stats.mmd2(p) for p in perms])
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.01, 0.001])
+@pytest.mark.parametrize("n", [5, 100])
+def test_normal_threshold_is_the_two_sided_normal_quantile(n, alpha):
+    """The normal acceptance bound is z_{1-alpha/2} standard deviations of
+    MMD^2 (a two-sided test): scipy's normal quantile, not erfinv, fixes it.
+    Catches erfinv(1 - alpha/2) (a one-sided bound)."""
+    sd = math.sqrt(2.0 * stats.kernel_variance(n) / P)
+    z = stats.normal_threshold(n, P, alpha) / sd
+    assert z == pytest.approx(float(scipy_stats.norm.ppf(1.0 - alpha / 2.0)), rel=1e-12)
+
+
+@pytest.mark.parametrize("n,samples", [(5, 800), (100, 400)])
+def test_mmd2_null_variance_and_z(n, samples):
+    """Under H0 the estimate over |Pi| permutations (|Pi|/2 disjoint pairs)
+    has mean 0 and variance 2 Var(K) / |Pi|: the sample variance of many
+    independent estimates lies in its chi-square 99.9% interval, and mmd_z
+    has standard deviation 1.  Catches a dropped or doubled factor 2 (the
+    variance would be off by 2x; the interval is about +-25%)."""
+    size = 1000
+    m = _null_mmd2(n, size, samples, seed=7 + n)
+    want = 2.0 * stats.kernel_variance(n) / size
+    lo = scipy_stats.chi2.ppf(0.0005, samples - 1) / (samples - 1)
+    hi = scipy_stats.chi2.ppf(0.9995, samples - 1) / (samples - 1)
+    ratio = float(np.var(m, ddof=1)) / want
+    assert lo < ratio < hi, ratio
+    assert abs(float(m.mean())) < 4.0 * math.sqrt(want / samples)
+    z = np.array([stats.mmd_z(n, v, size) for v in m])
+    assert lo < float(np.var(z, ddof=1)) < hi
+
+
+def test_mmd2_null_rejection_rate_is_alpha():
+    """The normal bound rejects about alpha of the null samples (4,000
+    estimates over |Pi| = 400 at n = 5; binomial sd 0.34%): a one-sided
+    quantile would reject about alpha/2, a doubled variance about 0.6%."""
+    size, samples = 400, 4000
+    m = _null_mmd2(5, size, samples, seed=99)
+    rate = float(np.mean(np.abs(m) >= stats.normal_threshold(5, size, 0.05)))
+    assert 0.036 < rate < 0.064, rate
+
+
+@pytest.mark.parametrize("sample_size", [1000, 100_000])
+@pytest.mark.parametrize("alpha", [0.05, 0.01])
+def test_hoeffding_threshold_holds_for_the_extreme_bounded_mean(sample_size, alpha):
+    """MMD^2 + E[K] is a mean of |Pi|/2 kernel values in [0, 1], so
+    Hoeffding's inequality bounds its deviation.  For the extreme [0, 1]
+    variable (Bernoulli 1/2) the exact two-sided binomial tail at the
+    threshold must not exceed alpha, and stays within a factor 20 of it.
+    Catches counting |Pi| values instead of |Pi|/2 pairs (the tail would
+    exceed alpha)."""
+    m = sample_size // 2
+    t = stats.hoeffding_threshold(sample_size, alpha)
+    k = math.floor(m * (0.5 - t))  # |S/m - 1/2| >= t  <=>  S <= m/2 - m t  or  S >= m/2 + m t
+    tail = 2.0 * float(scipy_stats.binom.cdf(k, m, 0.5))
+    assert alpha / 20 < tail <= alpha, tail
