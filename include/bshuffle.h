@@ -127,6 +127,34 @@ bs_status bs_shuffle(const void *in, void *out, uint64_t n, uint32_t elem_bytes,
                      uint32_t rounds, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * bs_shuffle_noalloc -- bs_shuffle for callers that cannot allocate device
+ * memory (code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc): the same result byte for byte, with no
+ * workspace argument.  Its kernels keep their tile status words and counters
+ * in a device array of static storage inside the library, one per GPU,
+ * BS_NOALLOC_SCRATCH_BYTES bytes (about 4 MiB), held until the process ends.
+ * No hipMalloc, hipFree or other allocating routine is ever called.
+ *
+ *   in, out, elem_bytes, seed, rounds, stream   as for bs_shuffle.
+ *   n           0 <= n <= BS_NOALLOC_MAX_ITEMS (2^30); larger n returns
+ *               BS_ENOMEM (the array is too small) and enqueues nothing.
+ *
+ * The first call on a device looks up that device's array and zero-fills it
+ * on `stream`; that first call must not be made while `stream` is capturing
+ * (BS_EINVAL): make one call outside capture first.  Later calls, captured
+ * or not, need nothing more: each launch leaves the array ready for the next.
+ * All calls on one GPU share its array, so two bs_shuffle_noalloc calls whose
+ * executions overlap on one GPU (different streams, or graphs replayed
+ * concurrently) race and give wrong results; serialize them.  Device-side
+ * errors are sticky in the array; there is no entry point to read them, so
+ * callers that need the look-back watchdog's report use bs_shuffle.
+ */
+#define BS_NOALLOC_MAX_ITEMS (((uint64_t)1) << 30)
+#define BS_NOALLOC_SCRATCH_BYTES (256u + (1u << 19) * 8u)
+bs_status bs_shuffle_noalloc(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                             uint32_t rounds, void *stream);
+
+/*
  * bs_shuffle_batched -- many independent shuffles in one launch sequence.
  *
  *   offsets     device int64[num_segments + 1], offsets[0] = 0, non-decreasing;

@@ -46,6 +46,7 @@ _SIGNATURES = {
     "bs_workspace_error": (_i32, [_vp, _vp]),
     "bs_shuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_shuffle_batched": (_i32, [_vp, _vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp, _sz, _vp]),
+    "bs_shuffle_noalloc": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp]),
     "bs_set_config": (_i32, [_u32, _u32, _u32, _u32]),
     "bs_get_config": (_i32, [_vp, _vp, _vp, _vp]),
     "bs_set_tuned_config": (_i32, [_u32, _u32, _u32, _u32, _u32, _u32, _u32]),
@@ -134,6 +135,13 @@ def bs_workspace_bytes(items: int, num_segments: int = 0, elem_bytes: int = 4) -
 def bs_shuffle(in_ptr, out_ptr, n, elem_bytes, seed, rounds, workspace, workspace_bytes, stream) -> int:
     return int(lib().bs_shuffle(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, workspace,
                                 workspace_bytes, stream))
+
+
+NOALLOC_MAX_ITEMS = 1 << 30
+
+
+def bs_shuffle_noalloc(in_ptr, out_ptr, n, elem_bytes, seed, rounds, stream) -> int:
+    return int(lib().bs_shuffle_noalloc(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, stream))
 
 
 def bs_shuffle_batched(in_ptr, out_ptr, offsets_ptr, seeds_ptr, num_segments, total_items, elem_bytes, rounds,

@@ -18,6 +18,11 @@
 #include "kernels.h"
 
 static_assert(BS_GRID_ONE_PER_TILE == bsd::kGridOnePerTile, "grid constant of the ABI");
+
+// Workspace of bs_shuffle_noalloc: a device array of static storage, one per
+// GPU, held until the process ends; every bs_shuffle_noalloc call on a GPU
+// uses that GPU's copy (never allocated or freed by the library).
+static __device__ __align__(256) uint8_t scratch[BS_NOALLOC_SCRATCH_BYTES];
 static_assert(BS_DEPTH_COMPACT == bsd::kDepthCompact, "schedule constant of the ABI");
 static_assert(BS_DEPTH_COMPACT_PIPE == bsd::kDepthCompactPipe, "schedule constant of the ABI");
 
@@ -32,6 +37,7 @@ bs_status hip_fail(hipError_t e) {
 
 // The smallest tile any launch configuration uses: sizes the status array.
 constexpr uint64_t kMinTile = 2048;  // indices; no compiled shape has a smaller tile
+constexpr uint32_t kStaticMaxDomainBits = 30;  // bs_shuffle_noalloc: domains up to 2^30 (n <= 2^30)
 constexpr size_t kHeaderBytes = sizeof(bsd::WorkspaceHeader);
 
 std::mutex g_mu;
@@ -207,6 +213,85 @@ bool ranges_overlap(const void* a, const void* b, uint64_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+// Argument checks shared by the single-shuffle entry points (synchronous,
+// before anything is enqueued).
+bs_status check_single_args(const void* in, const void* out, uint64_t n, uint32_t elem_bytes, uint32_t rounds) {
+  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
+  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
+  if (n == 0) return BS_OK;
+  if (!in || !out) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
+    return BS_EELEM;
+  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
+  return BS_OK;
+}
+
+// One fused shuffle launch (n > 0, arguments checked); g_mu held.
+bs_status launch_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t rounds,
+                         void* workspace, size_t workspace_bytes, hipStream_t s) {
+  const uint32_t k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
+  bsd::SingleArgs a = {};
+  setup_cipher(a, n, seed, rounds);
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  const bsd::LaunchConfig cfg = pick_config(0, elem_bytes, k);
+  const bool wide = k > 32;
+  const uint64_t tile = wide ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;
+  a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
+  const size_t need = align256(kHeaderBytes + single_capacity(n) * 8);
+  void* ws = nullptr;
+  bs_status st = resolve_workspace(workspace, workspace_bytes, need, s, &ws);
+  if (st != BS_OK) return st;
+  a.hdr = static_cast<bsd::WorkspaceHeader*>(ws);
+  a.status = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(ws) + kHeaderBytes);
+  a.capacity = uint32_t(single_capacity(n));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t cus = 0;
+  st = device_cus(dev, &cus);
+  if (st != BS_OK) return st;
+  e = bsd::launch_single(a, elem_bytes, g_nontemporal_store, cfg, cus, s);
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+// The workspace of bs_shuffle_noalloc is `scratch` (defined above the
+// namespace): the header plus one status word per 2,048 padded indices of a
+// domain of up to 2^30.  Host code must never pass `scratch` itself to a
+// kernel or a copy (in host code the name is a host-side stand-in): it uses
+// the device address that hipGetSymbolAddress returns, kept per device.
+constexpr size_t kStaticScratchBytes = kHeaderBytes + (size_t(1) << (kStaticMaxDomainBits - 11)) * 8;
+static_assert(kStaticScratchBytes == BS_NOALLOC_SCRATCH_BYTES, "scratch size of the ABI");
+std::map<int, void*> g_scratch;  // device -> address of `scratch` on that device
+
+// The current device's scratch address (g_mu held).  The first call on a
+// device looks the address up and zero-fills the array on `s` (a zero-filled
+// workspace is a valid one); that first call must not be captured into a
+// graph, because the fill would then only run when the graph does.
+bs_status static_scratch(hipStream_t s, void** ws) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    *ws = it->second;
+    return BS_OK;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return hip_fail(e);
+  if (cap != hipStreamCaptureStatusNone) return BS_EINVAL;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e);
+  if (reinterpret_cast<uintptr_t>(p) % 256 != 0) return BS_EINVAL;
+  e = bsd::launch_workspace_init(p, kStaticScratchBytes, s);
+  if (e != hipSuccess) return hip_fail(e);
+  g_scratch[dev] = p;
+  *ws = p;
+  return BS_OK;
+}
+
 }  // namespace
 
 namespace bsd {
@@ -362,42 +447,26 @@ bs_status bs_get_config(uint32_t* waves, uint32_t* items, uint32_t* depth, uint3
 
 bs_status bs_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t rounds,
                      void* workspace, size_t workspace_bytes, void* stream) {
-  if (!valid_elem_bytes(elem_bytes)) return BS_EELEM;
-  if (rounds > BS_MAX_ROUNDS || n > BS_MAX_ITEMS) return BS_EINVAL;
-  if (n == 0) return BS_OK;
-  if (!in || !out) return BS_EINVAL;
-  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % elem_bytes)
-    return BS_EELEM;
-  if (ranges_overlap(in, out, n * elem_bytes)) return BS_EALIAS;
-
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint32_t k = bs_domain_bits(n);
-  bsd::SingleArgs a = {};
-  setup_cipher(a, n, seed, rounds);
-  a.in = static_cast<const uint8_t*>(in);
-  a.out = static_cast<uint8_t*>(out);
-
+  const bs_status st = check_single_args(in, out, n, elem_bytes, rounds);
+  if (st != BS_OK || n == 0) return st;
   std::lock_guard<std::mutex> lock(g_mu);
-  const bsd::LaunchConfig cfg = pick_config(0, elem_bytes, k);
-  const bool wide = k > 32;
-  const uint64_t tile = wide ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;
-  a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
-  const size_t need = bs_workspace_bytes(n, 0, elem_bytes);
-  void* ws = nullptr;
-  bs_status st = resolve_workspace(workspace, workspace_bytes, need, s, &ws);
-  if (st != BS_OK) return st;
-  a.hdr = static_cast<bsd::WorkspaceHeader*>(ws);
-  a.status = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(ws) + kHeaderBytes);
-  a.capacity = uint32_t(single_capacity(n));
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e);
-  uint32_t cus = 0;
-  st = device_cus(dev, &cus);
-  if (st != BS_OK) return st;
-  e = bsd::launch_single(a, elem_bytes, g_nontemporal_store, cfg, cus, s);
-  return e == hipSuccess ? BS_OK : hip_fail(e);
+  return launch_shuffle(in, out, n, elem_bytes, seed, rounds, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream));
 }
+
+bs_status bs_shuffle_noalloc(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                             uint32_t rounds, void* stream) {
+  const bs_status st = check_single_args(in, out, n, elem_bytes, rounds);
+  if (st != BS_OK || n == 0) return st;
+  if (bs_workspace_bytes(n, 0, elem_bytes) > kStaticScratchBytes) return BS_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  void* ws = nullptr;
+  const bs_status sst = static_scratch(s, &ws);
+  if (sst != BS_OK) return sst;
+  return launch_shuffle(in, out, n, elem_bytes, seed, rounds, ws, kStaticScratchBytes, s);
+}
+
 
 bs_status bs_shuffle_batched(const void* in, void* out, const int64_t* offsets, const uint64_t* seeds,
                              uint32_t num_segments, uint64_t total_items, uint32_t elem_bytes, uint32_t rounds,

@@ -294,3 +294,14 @@ def test_tensor_wrappers_check_out_and_devices(monkeypatch):
     with pytest.raises(ValueError, match="seeds must be on"):
         B.shuffle_batched(x, off, torch.zeros(2, dtype=torch.int64))
 
+
+def test_noalloc_argument_checks():
+    """bs_shuffle_noalloc rejects what bs_shuffle rejects, and n above its
+    static array's limit (2^30 records) with BS_ENOMEM, before any device work."""
+    assert B.bs_shuffle_noalloc(None, None, 0, 4, 1, 24, None) == B.BS_OK
+    assert B.bs_shuffle_noalloc(FAKE_IN, FAKE_OUT, 10, 3, 1, 24, None) == B.BS_EELEM
+    assert B.bs_shuffle_noalloc(FAKE_IN, FAKE_OUT, 10, 4, 1, 65, None) == B.BS_EINVAL
+    assert B.bs_shuffle_noalloc(None, FAKE_OUT, 10, 4, 1, 24, None) == B.BS_EINVAL
+    assert B.bs_shuffle_noalloc(FAKE_IN, FAKE_IN, 10, 4, 1, 24, None) == B.BS_EALIAS
+    assert B.bs_shuffle_noalloc(FAKE_IN, FAKE_OUT, B.NOALLOC_MAX_ITEMS + 1, 4, 1, 24, None) == B.BS_ENOMEM
+
