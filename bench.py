@@ -89,11 +89,21 @@ def parse_args():
     p.add_argument("--fusion-sweep", action="store_true",
                    help="also time every fusion form over n = 2^20 .. 2^29 (+1)")
     p.add_argument("--no-large", action="store_true")
-    p.add_argument("--sweep", action="store_true",
-                   help="also time the fused kernel and the gather probe over n = 2^w, 2^w+1 (w = 8..30), u32 and u64")
+    p.add_argument("--no-sweep", action="store_true",
+                   help="skip the size sweep (fused kernel beside the same-footprint random-read ceiling over "
+                        "n = 2^w, 2^w+1, w = 8..30, u32 and u64)")
+    p.add_argument("--gather-sweep", action="store_true",
+                   help="add a random gather with an index array to every sweep point")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-serving", action="store_true")
-    p.add_argument("--serve-requests", type=int, default=2000)
+    p.add_argument("--serve-requests", type=int, default=100_000)
+    p.add_argument("--serve-loads", default="0.5,0.8", help="open-loop rates as fractions of the closed-loop capacity")
+    p.add_argument("--profile-footprint", action="store_true",
+                   help="profiler run: a copy of known size, then the random-read probe over every footprint and "
+                        "record size; no extras")
+    p.add_argument("--profile-large", action="store_true",
+                   help="profiler run: a copy of known size, then the large workloads (10^9 uint32, 2.5e8 x 16 B) "
+                        "and the u64 n = 2^27+1 shuffle, --steps each; no extras")
     p.add_argument("--profile", action="store_true",
                    help="profiler run: one copy of known size, then the steps; no extras")
     p.add_argument("--profile-batched", action="store_true",
@@ -243,42 +253,46 @@ def _pinned_trials(fn, trials: int) -> list[float]:
             os.sched_setaffinity(0, old)
 
 
-def cpu_baseline(trials: int = 5) -> dict:
-    """The oracle, single thread pinned to one core, on a bounded sample of the
-    same workload: mean of `trials` runs."""
+def cpu_baseline(x, y_gpu, trials: int = 3) -> dict:
+    """The oracle, single thread pinned to one core, on the headline's own
+    input bytes (n = 2^27+1 uint32, seed 7, 24 rounds): mean of `trials`
+    runs.  Its output is compared whole with the GPU's output of the timed
+    steps."""
     import numpy as np
 
     import oracle
-    from paper_2106_06161_amd import workloads as W
 
-    n = (1 << 25) + 1  # same padding ratio as the headline (domain 2^26)
-    x = W.uniform_u32(n, seed=SEED)
-    out = oracle.shuffle(x, SEED, ROUNDS)
-    assert out.shape == x.shape and np.uint64(out.sum(dtype=np.uint64)) == np.uint64(x.sum(dtype=np.uint64))
-    times = _pinned_trials(lambda: oracle.shuffle(x, SEED, ROUNDS), trials)
+    n = x.shape[0]
+    first = {}
+
+    def run():
+        out = oracle.shuffle(x, SEED, ROUNDS)
+        first.setdefault("out", out)
+
+    times = _pinned_trials(run, trials)
+    same = bool(np.array_equal(first["out"], y_gpu))
     dt = sum(times) / len(times)
     return {
         "value": n / dt / 1e9,
         "unit": "Gelem/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"n=2^25+1 uint32 uniform (PCG64 seed 7), seed 7, {ROUNDS} rounds, domain 2^26; mean of "
-                  f"{trials} runs ({dt:.2f} s each, min {min(times):.2f} s) pinned to one core of {cpu_model()} "
-                  f"({os.cpu_count()} logical CPUs)",
+        "sample": f"the headline workload itself: n=2^27+1 uint32 uniform (PCG64 seed 7), seed 7, {ROUNDS} rounds, "
+                  f"domain 2^28; mean of {trials} runs ({dt:.2f} s each, min {min(times):.2f} s) pinned to one "
+                  f"core of {cpu_model()} ({os.cpu_count()} logical CPUs)",
+        "gpu_output_equal": same,
     }
 
 
-def cpu_std_shuffle(trials: int = 5) -> dict:
-    """std::shuffle (Fisher-Yates, std::mt19937_64), one thread pinned to one core, same sample bytes."""
+def cpu_std_shuffle(x, trials: int = 3) -> dict:
+    """std::shuffle (Fisher-Yates, std::mt19937_64), one thread pinned to one core, same input bytes."""
     import oracle
-    from paper_2106_06161_amd import workloads as W
 
-    n = (1 << 25) + 1
-    x = W.uniform_u32(n, seed=SEED)
+    n = x.shape[0]
     times = _pinned_trials(lambda: oracle.std_shuffle_u32(x, SEED), trials)
     dt = sum(times) / len(times)
     return {"value": n / dt / 1e9, "unit": "Gelem/s", "cores": 1, "kind": "std::shuffle",
-            "sample": f"n=2^25+1 uint32 (same bytes as cpu_baseline), std::mt19937_64(7), mean of {trials} runs "
+            "sample": f"n=2^27+1 uint32 (the headline's input bytes), std::mt19937_64(7), mean of {trials} runs "
                       f"({dt:.3f} s each) pinned to one core of {cpu_model()}"}
 
 
@@ -495,10 +509,45 @@ def bench_small(torch, bs, dev, timer) -> dict:
             "graph_launch_floor_us": t_floor * 1e6}
 
 
-def bench_large(torch, bs, dev, timer, rounds) -> dict:
+FOOTPRINTS_MIB = [32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]
+
+
+def random_read_rate(B, torch, timer, buf, region_bytes: int, eb: int, reads: int, sp) -> float:
+    """Random reads per second (G/s) of eb-byte records at hashed indices over
+    region_bytes of buf (bs_probe_random_reads_region)."""
+    out = torch.empty(reads // 16, dtype=torch.int32, device=buf.device)
+    t = timer.run(lambda: B._check(B.bs_probe_random_reads_region(buf.data_ptr(), region_bytes, eb, reads,
+                                                                  out.data_ptr(), 3, sp),
+                                   "bs_probe_random_reads_region"), 5)
+    del out
+    return reads / t / 1e9
+
+
+def bench_footprint(torch, B, dev, stream, timer) -> list:
+    """The random-read ceiling against the region read (32 MiB .. 8 GiB) and
+    the record size (4, 8, 16 B): 2^27 reads per point."""
+    sp = stream.cuda_stream
+    buf = torch.zeros(FOOTPRINTS_MIB[-1] << 18, dtype=torch.int32, device=dev)
+    rows = []
+    for eb in (4, 8, 16):
+        for mib in FOOTPRINTS_MIB:
+            log(f"bench: random reads, {eb}-byte records over {mib} MiB")
+            rate = random_read_rate(B, torch, timer, buf, mib << 20, eb, 1 << 27, sp)
+            rows.append({"elem_bytes": eb, "region_MiB": mib, "G_reads_s": rate, "GBps_useful": rate * eb})
+    del buf
+    return rows
+
+
+def bench_large(torch, bs, B, dev, stream, timer, rounds) -> dict:
     """n = 10^9 uint32 arange (seed 1, domain 2^30) and 2.5e8 records of four
-    float32 (seeded device normal values, seed 11, domain 2^28)."""
+    float32 (seeded device normal values, seed 11, domain 2^28), each beside
+    the random-read ceiling over the same footprint (4 GiB) and record size."""
+    sp = stream.cuda_stream
     res = {}
+    probe = torch.zeros(1 << 30, dtype=torch.int32, device=dev)  # 4 GiB
+    for name, eb in (("u32", 4), ("rec16", 16)):
+        res[f"ceiling_{name}_4GiB_G_reads_s"] = random_read_rate(B, torch, timer, probe, 4 << 30, eb, 1 << 28, sp)
+    del probe
     n = 10**9
     x = torch.arange(n, dtype=torch.int32, device=dev)
     y = torch.empty_like(x)
@@ -507,6 +556,8 @@ def bench_large(torch, bs, dev, timer, rounds) -> dict:
     res["u32_1e9_ms"] = t * 1e3
     res["u32_1e9_Gelem_s"] = n / t / 1e9
     res["u32_1e9_alg_GBps"] = 8.0 * n / t / 1e9
+    res["u32_1e9_pct_of_same_footprint_ceiling"] = 100.0 * res["u32_1e9_Gelem_s"] / res["ceiling_u32_4GiB_G_reads_s"]
+    res["u32_1e9_launch"] = list(B.bs_query_config(0, 4, n))
     del x, y
     n = 250_000_000
     gen = torch.Generator(device=dev).manual_seed(11)
@@ -516,58 +567,78 @@ def bench_large(torch, bs, dev, timer, rounds) -> dict:
     res["rec16_2p5e8_ms"] = t * 1e3
     res["rec16_2p5e8_Gelem_s"] = n / t / 1e9
     res["rec16_2p5e8_alg_GBps"] = 32.0 * n / t / 1e9
+    res["rec16_2p5e8_pct_of_same_footprint_ceiling"] = (100.0 * res["rec16_2p5e8_Gelem_s"]
+                                                       / res["ceiling_rec16_4GiB_G_reads_s"])
+    res["rec16_2p5e8_launch"] = list(B.bs_query_config(0, 16, n))
     del x, y
     if bs.workspace_error(ws) != 0:
         raise RuntimeError("device-side error in the large workloads")
     return res
 
 
-def bench_sweep(torch, bs, B, dev, stream, timer, rounds) -> list:
-    """The fused kernel and a random gather with an index array over
-    n = 2^w and 2^w + 1, w = 8..30, for 4- and 8-byte records."""
+def bench_sweep(torch, bs, B, dev, stream, timer, rounds, gather: bool = False) -> list:
+    """Sec. 6's protocol on this chip: the fused kernel over n = 2^w and
+    2^w + 1, w = 8..30, for 4- and 8-byte records (mean of 5 launches), beside
+    the random-read ceiling at the same record size over a region of 2^w
+    records (the same footprint), and optionally a random gather with an
+    index array."""
     out = []
     sp = stream.cuda_stream
     for eb, dt in ((4, torch.int32), (8, torch.int64)):
         for w in range(8, 31):
+            x = torch.arange((1 << w) + 1, dtype=torch.int64, device=dev).to(dt)
+            y = torch.empty_like(x)
+            ws = bs.make_workspace(bs.workspace_bytes((1 << w) + 1), device=dev)
+            reads = max(1 << 16, ((1 << w) + 15) // 16 * 16)
+            ceil = random_read_rate(B, torch, timer, x, (1 << w) * eb, eb, reads, sp)
             for n in (1 << w, (1 << w) + 1):
-                if n * eb * 3 > 24 << 30:
-                    continue
                 log(f"bench: sweep elem_bytes={eb} n={n}")
-                x = torch.arange(n, dtype=torch.int64, device=dev).to(dt)
-                y = torch.empty_like(x)
-                ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
-                t = timer.run(lambda: bs.shuffle(x, SEED, rounds, out=y, workspace=ws), 5)
-                idx = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
-                tg = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), n, y.data_ptr(), idx.data_ptr(), n, eb, sp), 5)
-                out.append({"elem_bytes": eb, "n": n, "shuffle_ms": t * 1e3, "gather_ms": tg * 1e3,
-                            "Gelem_s": n / t / 1e9, "launch": list(B.bs_query_config(0, eb, n))})
-                if bs.workspace_error(ws) != 0:
-                    raise RuntimeError("device-side error in the sweep")
-                del x, y, idx, ws
+                xs, ys = x[:n], y[:n]
+                t = timer.run(lambda: bs.shuffle(xs, SEED, rounds, out=ys, workspace=ws), 5)
+                row = {"elem_bytes": eb, "n": n, "shuffle_ms": t * 1e3, "Gelem_s": n / t / 1e9,
+                       "random_read_ceiling_G_s": ceil, "pct_of_ceiling": 100.0 * (n / t / 1e9) / ceil,
+                       "launch": list(B.bs_query_config(0, eb, n))}
+                if gather:
+                    idx = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
+                    tg = timer.run(lambda: B.bs_probe_gather(xs.data_ptr(), n, ys.data_ptr(), idx.data_ptr(), n,
+                                                             eb, sp), 5)
+                    row["gather_ms"] = tg * 1e3
+                    del idx
+                out.append(row)
+            if bs.workspace_error(ws) != 0:
+                raise RuntimeError("device-side error in the sweep")
+            del x, y, ws
     return out
 
 
-def bench_serving(rounds: int, count: int) -> dict:
-    """The continuous-batching server: closed-loop capacity (every request
-    arrives at once), then Poisson arrivals at 0.8x that rate."""
+def bench_serving(rounds: int, count: int, loads) -> dict:
+    """The continuous-batching server on `count` requests: closed-loop
+    capacity C (every request arrives at once), then Poisson arrivals at each
+    fraction of C in `loads`.  Admission budget: the device's free memory."""
     from paper_2106_06161_amd.serve import HipExecutor, ShuffleServer, make_requests
 
     ex = HipExecutor(streams=4, rounds=rounds, pool_items=1 << 27)
-    srv = ShuffleServer(ex, budget_bytes=32 << 30)
+    srv = ShuffleServer(ex)
     cap = srv.run(make_requests(count, 1000, 100_000_000, qps=1e12, seed=5)).summary()
-    qps = 0.8 * cap["requests_per_s"]
-    run = srv.run(make_requests(count, 1000, 100_000_000, qps=qps, seed=6)).summary()
-    return {
+    log(f"bench: serving closed loop {cap['requests_per_s']:.0f} requests/s, {cap['failed']} failed")
+    res = {
         "workload": f"{count} requests per run, sizes floor(exp(U(ln 1e3, ln 1e8))), dtype uniform over "
-                    "uint32/int64/float32, 64-bit seeds (PCG64 5 and 6); payloads resident in HBM; "
-                    "HBM budget 32 GiB of outputs, 4 streams, requests <= 2^20 records coalesced",
+                    "uint32/int64/float32, 64-bit seeds (PCG64 5, then 6); payloads resident in HBM; admission "
+                    "budget = free device memory at the start of each run; 4 streams, requests <= 2^20 records "
+                    "coalesced",
         "closed_loop": cap,
-        "open_loop_qps": qps,
-        "open_loop": run,
-        "p50_ms": run["latency_p50_ms"],
-        "p99_ms": run["latency_p99_ms"],
-        "device_error": int(ex.check_errors()),
+        "open_loop": [],
     }
+    for f in loads:
+        qps = f * cap["requests_per_s"]
+        run = srv.run(make_requests(count, 1000, 100_000_000, qps=qps, seed=6)).summary()
+        log(f"bench: serving at {f} C: p50 {run['latency_p50_ms']:.2f} ms, p99 {run['latency_p99_ms']:.2f} ms, "
+            f"{run['failed']} failed")
+        res["open_loop"].append(dict(run, load=f, qps=qps))
+    res["p50_ms"] = {str(r["load"]): r["latency_p50_ms"] for r in res["open_loop"]}
+    res["p99_ms"] = {str(r["load"]): r["latency_p99_ms"] for r in res["open_loop"]}
+    res["device_error"] = int(ex.check_errors())
+    return res
 
 
 def main() -> int:
@@ -609,11 +680,46 @@ def main() -> int:
             f"device status {err}")
         return 1 if err else 0
 
+    if args.profile_footprint:
+        nb = 512 << 20
+        src = torch.zeros(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        B._check(B.bs_probe_copy(src.data_ptr(), dst.data_ptr(), nb, sp), "bs_probe_copy")
+        torch.cuda.synchronize()
+        del src, dst
+        rows = bench_footprint(torch, B, dev, stream, timer)
+        print(json.dumps({"footprint": rows}), flush=True)
+        return 0
+
+    if args.profile_large:
+        nb = 512 << 20
+        src = torch.zeros(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        B._check(B.bs_probe_copy(src.data_ptr(), dst.data_ptr(), nb, sp), "bs_probe_copy")
+        torch.cuda.synchronize()
+        del src, dst
+        res = {}
+        for name, n, shape, dt, seed in (("u32_1e9", 10**9, (10**9,), torch.int32, 1),
+                                         ("rec16_2p5e8", 250_000_000, (250_000_000, 4), torch.float32, 11),
+                                         ("u64_2p27p1", N_HEADLINE, (N_HEADLINE,), torch.int64, SEED)):
+            log(f"bench: profile {name}")
+            x = torch.zeros(shape, dtype=dt, device=dev)
+            y = torch.empty_like(x)
+            ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+            for _ in range(args.steps):
+                bs.shuffle(x, seed, rounds, out=y, workspace=ws)
+            torch.cuda.synchronize()
+            if bs.workspace_error(ws) != 0:
+                raise RuntimeError(f"device-side error in {name}")
+            res[name] = list(B.bs_query_config(0, x.element_size() * (x.numel() // n), n))
+            del x, y, ws
+        print(json.dumps({"launch": res}), flush=True)
+        return 0
+
     log("bench: generating the headline input (n=2^27+1 uint32, PCG64 seed 7)")
     x_np = W.uniform_u32(N_HEADLINE, seed=SEED)
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
-    del x_np
     ws = bs.make_workspace(bs.workspace_bytes(N_HEADLINE), device=dev)
 
     if args.profile:
@@ -649,6 +755,7 @@ def main() -> int:
         log(f"bench: device-side error {B.status_string(err)}")
         return 1
     log(f"bench: {wall / args.steps * 1e3:.3f} ms/step wall, {kernel_s * 1e3:.3f} ms kernel")
+    y_timed = y.cpu().numpy()  # the timed steps' output, checked whole against the oracle in the CPU leg
 
     alg_bytes = 2 * 4 * N_HEADLINE
     achieved = alg_bytes / kernel_s / 1e9
@@ -691,7 +798,10 @@ def main() -> int:
         },
     }
     if traffic:
-        result["roofline"]["physical_GBps"] = traffic["hbm_bytes_per_launch"] / kernel_s / 1e9
+        # FETCH_SIZE and WRITE_SIZE count what the L2s exchange with the data
+        # fabric; the fabric serves part of it from the Infinity Cache, so
+        # this is an upper bound on DRAM traffic, not DRAM traffic
+        result["roofline"]["l2_fabric_GBps"] = traffic["hbm_bytes_per_launch"] / kernel_s / 1e9
         result["roofline"]["fetch_bytes_per_elem"] = traffic["fetch_bytes_per_launch"] / N_HEADLINE
         result["roofline"]["write_bytes_per_elem"] = traffic["write_bytes_per_launch"] / N_HEADLINE
         result["roofline"]["traffic_kernel_ms_rocprof"] = traffic["kernel_avg_ms_rocprof"]
@@ -752,9 +862,13 @@ def main() -> int:
     if not args.no_large:
         log("bench: small (n=100,000, 4 rounds) and large (10^9 uint32; 2.5e8 x 16-byte records) workloads")
         result["small"] = bench_small(torch, bs, dev, timer)
-        result["large"] = bench_large(torch, bs, dev, timer, rounds)
-    if args.sweep:
-        result["sweep"] = bench_sweep(torch, bs, B, dev, stream, timer, rounds)
+        result["large"] = bench_large(torch, bs, B, dev, stream, timer, rounds)
+    if not args.no_ceilings:
+        log("bench: random-read ceiling against footprint and record size")
+        result["random_reads_by_footprint"] = bench_footprint(torch, B, dev, stream, timer)
+    if not args.no_sweep:
+        log("bench: size sweep (n = 2^w and 2^w+1, w = 8..30; uint32 and uint64)")
+        result["sweep"] = bench_sweep(torch, bs, B, dev, stream, timer, rounds, gather=args.gather_sweep)
 
     if not args.no_batched:
         log("bench: batched vs per-call (4,096 segments, log-uniform sizes in [100, 10^6], PCG64 seed 3)")
@@ -765,12 +879,17 @@ def main() -> int:
     if not args.no_serving:
         log(f"bench: serving ({args.serve_requests} requests, sizes log-uniform in [10^3, 10^8], "
             "dtype uniform over uint32/int64/float32)")
-        result["serving"] = bench_serving(rounds, args.serve_requests)
+        loads = [float(v) for v in args.serve_loads.split(",") if v]
+        result["serving"] = bench_serving(rounds, args.serve_requests, loads)
 
     if not args.no_cpu_baseline:
         log("bench: CPU baseline (oracle, one thread, bounded sample) and std::shuffle")
-        result["cpu_baseline"] = cpu_baseline()
-        result["cpu_std_shuffle"] = cpu_std_shuffle()
+        result["cpu_baseline"] = cpu_baseline(x_np, y_timed)
+        result["cpu_std_shuffle"] = cpu_std_shuffle(x_np)
+        if not result["cpu_baseline"]["gpu_output_equal"]:
+            log("bench: the timed GPU output differs from the oracle's")
+            print(json.dumps(result), flush=True)
+            return 1
     print(json.dumps(result), flush=True)
     return 0
 

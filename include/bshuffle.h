@@ -103,6 +103,21 @@ bs_status bs_workspace_init(void *workspace, size_t workspace_bytes, void *strea
 bs_status bs_workspace_error(void *workspace, void *stream);
 
 /*
+ * The same, without blocking: enqueues on `stream` a one-thread kernel that
+ * writes BS_OK, BS_ETIMEOUT or BS_EDEVICE to *status and clears the
+ * workspace's error word, so the status covers exactly the work enqueued on
+ * `stream` since the previous read.  `status` is device-writable memory (a
+ * device buffer, or pinned host memory from hipHostMalloc) of 4 bytes,
+ * 4-byte aligned; it holds the result once the stream has reached this point
+ * (an event recorded after this call has completed).  `workspace` is a
+ * caller's workspace (256-byte aligned; there is no NULL form).  BS_EINVAL for
+ * null or misaligned pointers.  Capturable in a graph.  Serving loops use it
+ * to fail exactly the launch whose look-back timed out or whose batch was
+ * malformed (Algorithm 1's scan is the step that can report either).
+ */
+bs_status bs_workspace_error_async(void *workspace, int32_t *status, void *stream);
+
+/*
  * bs_shuffle -- one bijective shuffle (Algorithm 1, fused in a single pass).
  *
  *   in, out     device buffers of n records of elem_bytes bytes each; they

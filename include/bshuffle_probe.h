@@ -30,6 +30,18 @@ bs_status bs_probe_copy(const void *in, void *out, uint64_t bytes, void *stream)
  * traffic. */
 bs_status bs_probe_random_reads(const void *in, uint64_t words, void *out, uint32_t salt, void *stream);
 
+/* The same ceiling over a chosen footprint and record size: `reads` random
+ * reads of elem_bytes (4, 8 or 16; BS_EELEM otherwise) at hashed record
+ * indices inside the first region_bytes of `in` (region_bytes / elem_bytes a
+ * power of two in [1, 2^32]), 16 per lane, all in flight at once; out holds
+ * reads/16 uint32 (one per lane).  reads is a multiple of 16, at most 2^36
+ * (BS_EINVAL otherwise).  Separates the rate of random reads from the size of
+ * the region they land in (caches, address translation) and from the bytes
+ * each one carries.  bs_probe_random_reads(in, w, ...) is
+ * bs_probe_random_reads_region(in, 4w, 4, w, ...). */
+bs_status bs_probe_random_reads_region(const void *in, uint64_t region_bytes, uint32_t elem_bytes, uint64_t reads,
+                                       void *out, uint32_t salt, void *stream);
+
 /* Random gather with an index array: out[j] = in[idx[j]] for j < n, records
  * of elem_bytes (1,2,4,8,16); idx is a device uint32 array whose entries must
  * be < n_in (checked on the device: an out-of-range index is skipped). */

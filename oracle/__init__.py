@@ -286,3 +286,15 @@ def std_shuffle_u32(x: np.ndarray, seed: int) -> np.ndarray:
     y = np.array(x, dtype=np.uint32, copy=True)
     lib.cpu_std_shuffle_u32(_ptr(y), len(y), seed & (2**64 - 1))
     return y
+
+
+def std_permutations(n: int, count: int, first_seed: int = 1) -> np.ndarray:
+    """Row p is arange(n) shuffled by std::shuffle with std::mt19937_64(first_seed + p):
+    the control generator of the statistical tests (Sec. 5 compares against it)."""
+    build()
+    lib = ctypes.CDLL(_STD_LIB)
+    lib.cpu_std_permutations_u32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    lib.cpu_std_permutations_u32.restype = None
+    out = np.empty((count, n), dtype=np.uint32)
+    lib.cpu_std_permutations_u32(_ptr(out), n, count, first_seed & (2**64 - 1))
+    return out

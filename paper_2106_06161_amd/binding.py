@@ -44,6 +44,7 @@ _SIGNATURES = {
     "bs_workspace_bytes": (_sz, [_u64, _u32, _u32]),
     "bs_workspace_init": (_i32, [_vp, _sz, _vp]),
     "bs_workspace_error": (_i32, [_vp, _vp]),
+    "bs_workspace_error_async": (_i32, [_vp, _vp, _vp]),
     "bs_shuffle": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_shuffle_batched": (_i32, [_vp, _vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp, _sz, _vp]),
     "bs_shuffle_noalloc": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp]),
@@ -68,6 +69,7 @@ _SIGNATURES = {
     "bs_probe_copy": (_i32, [_vp, _vp, _u64, _vp]),
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
     "bs_probe_random_reads": (_i32, [_vp, _u64, _vp, _u32, _vp]),
+    "bs_probe_random_reads_region": (_i32, [_vp, _u64, _u32, _u64, _vp, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
     "bs_probe_set_store_mode": (_i32, [_u32]),
     "bs_probe_set_xcd_mode": (_i32, [_u32]),
@@ -272,6 +274,10 @@ def bs_probe_set_watchdog(spin_limit: int, stall_first_tile: int) -> int:
 
 def bs_probe_random_reads(in_ptr, words, out_ptr, salt, stream) -> int:
     return int(lib().bs_probe_random_reads(in_ptr, words, out_ptr, salt, stream))
+
+
+def bs_probe_random_reads_region(in_ptr, region_bytes, elem_bytes, reads, out_ptr, salt, stream) -> int:
+    return int(lib().bs_probe_random_reads_region(in_ptr, region_bytes, elem_bytes, reads, out_ptr, salt, stream))
 
 
 def bs_probe_set_batch_small(enable: int) -> int:
@@ -479,3 +485,20 @@ def workspace_error(workspace=None, stream=None, device=None) -> int:
     sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
     with torch.cuda.device(dev):
         return bs_workspace_error(workspace.data_ptr() if workspace is not None else None, sp)
+
+
+def workspace_error_async(workspace, status, stream=None) -> None:
+    """Enqueues on the stream a read-and-clear of the workspace's error word
+    into status[0] (a 4-byte int32 tensor on the device or in pinned host
+    memory); status[0] holds BS_OK / BS_ETIMEOUT / BS_EDEVICE once the stream
+    has passed this point."""
+    import torch
+
+    if status.dtype != torch.int32 or status.numel() < 1:
+        raise ValueError("status must be an int32 tensor with at least one element")
+    if not (status.is_cuda or status.is_pinned()):
+        raise ValueError("status must be device memory or pinned host memory")
+    sp = _stream_ptr(workspace, stream)
+    with torch.cuda.device(workspace.device):
+        _check(lib().bs_workspace_error_async(workspace.data_ptr(), status.data_ptr(), sp),
+               "bs_workspace_error_async")

@@ -388,6 +388,14 @@ bs_status bs_workspace_error(void* workspace, void* stream) {
   return BS_OK;
 }
 
+bs_status bs_workspace_error_async(void* workspace, int32_t* status, void* stream) {
+  if (!workspace || !status) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0 || reinterpret_cast<uintptr_t>(status) % 4 != 0)
+    return BS_EINVAL;
+  hipError_t e = bsd::launch_take_error(workspace, status, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
 bs_status bs_set_config(uint32_t waves, uint32_t items, uint32_t depth, uint32_t grid_mult) {
   std::lock_guard<std::mutex> lock(g_mu);
   if (waves == 0 && items == 0 && depth == 0 && grid_mult == 0) {

@@ -123,6 +123,7 @@ hipError_t launch_single(const SingleArgs& a, uint32_t elem_bytes, bool nontempo
 hipError_t launch_batched(const BatchArgs& a, uint32_t elem_bytes, const LaunchConfig& cfg, uint32_t num_cus,
                           hipStream_t stream);
 hipError_t launch_workspace_init(void* ws, size_t bytes, hipStream_t stream);
+hipError_t launch_take_error(void* ws, int32_t* status, hipStream_t stream);
 hipError_t launch_variant(const SingleArgs& a, uint32_t variant, uint32_t elem_bytes, uint32_t num_cus,
                           hipStream_t stream);
 hipError_t launch_tile_counts(const SingleArgs& a, hipStream_t stream);

@@ -59,16 +59,22 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
-__global__ __launch_bounds__(256) void random_reads_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+// T is the record read (4, 8 or 16 bytes); the sum of every record's first
+// word is stored, so no load can be dropped.
+__device__ __forceinline__ uint32_t first_word(uint32_t v) { return v; }
+__device__ __forceinline__ uint32_t first_word(u32x2 v) { return v.x ^ v.y; }
+__device__ __forceinline__ uint32_t first_word(u32x4 v) { return v.x ^ v.y ^ v.z ^ v.w; }
+template <typename T>
+__global__ __launch_bounds__(256) void random_reads_kernel(const T* __restrict__ in, uint32_t* __restrict__ out,
                                                            uint32_t mask, uint64_t lanes, uint32_t salt) {
   const uint64_t t = uint64_t(blockIdx.x) * 256 + threadIdx.x;
   if (t >= lanes) return;
-  uint32_t v[kRandomReads];
+  T v[kRandomReads];
 #pragma unroll
   for (int k = 0; k < kRandomReads; ++k) v[k] = in[hash32(uint32_t(t) * kRandomReads + k + salt) & mask];
   uint32_t sum = 0;
 #pragma unroll
-  for (int k = 0; k < kRandomReads; ++k) sum += v[k];
+  for (int k = 0; k < kRandomReads; ++k) sum += first_word(v[k]);
   out[t] = sum;
 }
 
@@ -110,13 +116,37 @@ bs_status bs_probe_copy(const void* in, void* out, uint64_t bytes, void* stream)
 }
 
 bs_status bs_probe_random_reads(const void* in, uint64_t words, void* out, uint32_t salt, void* stream) {
+  return bs_probe_random_reads_region(in, words * 4, 4, words, out, salt, stream);
+}
+
+bs_status bs_probe_random_reads_region(const void* in, uint64_t region_bytes, uint32_t elem_bytes, uint64_t reads,
+                                       void* out, uint32_t salt, void* stream) {
   if (!in || !out) return BS_EINVAL;
-  if (words < kRandomReads || words > (uint64_t(1) << 32) || (words & (words - 1)) != 0) return BS_EINVAL;
-  if (reinterpret_cast<uintptr_t>(in) % 4 || reinterpret_cast<uintptr_t>(out) % 4) return BS_EELEM;
-  const uint64_t lanes = words / kRandomReads;
-  hipLaunchKernelGGL(random_reads_kernel, dim3(uint32_t((lanes + 255) / 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), static_cast<const uint32_t*>(in), static_cast<uint32_t*>(out),
-                     uint32_t(words - 1), lanes, salt);
+  if (elem_bytes != 4 && elem_bytes != 8 && elem_bytes != 16) return BS_EELEM;
+  if (reinterpret_cast<uintptr_t>(in) % elem_bytes || reinterpret_cast<uintptr_t>(out) % 4) return BS_EELEM;
+  const uint64_t records = region_bytes / elem_bytes;
+  if (region_bytes % elem_bytes || records < 1 || records > (uint64_t(1) << 32) || (records & (records - 1)) != 0)
+    return BS_EINVAL;
+  if (reads < kRandomReads || reads % kRandomReads || reads / kRandomReads > (uint64_t(1) << 32)) return BS_EINVAL;
+  const uint64_t lanes = reads / kRandomReads;
+  const dim3 grid(uint32_t((lanes + 255) / 256));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t mask = uint32_t(records - 1);
+  uint32_t* o = static_cast<uint32_t*>(out);
+  switch (elem_bytes) {
+    case 4:
+      hipLaunchKernelGGL(random_reads_kernel<uint32_t>, grid, dim3(256), 0, s, static_cast<const uint32_t*>(in), o,
+                         mask, lanes, salt);
+      break;
+    case 8:
+      hipLaunchKernelGGL(random_reads_kernel<u32x2>, grid, dim3(256), 0, s, static_cast<const u32x2*>(in), o, mask,
+                         lanes, salt);
+      break;
+    default:
+      hipLaunchKernelGGL(random_reads_kernel<u32x4>, grid, dim3(256), 0, s, static_cast<const u32x4*>(in), o, mask,
+                         lanes, salt);
+      break;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     g_probe_hip_error = int32_t(e);

@@ -4,6 +4,7 @@
 #include <map>
 #include <utility>
 
+#include "bshuffle.h"
 #include "shuffle_impl.h"
 
 namespace bsd {
@@ -168,6 +169,13 @@ __global__ void zero_fill_kernel(uint32_t* p, uint64_t words, uint32_t capacity_
   constexpr uint64_t kCapacityWord = offsetof(WorkspaceHeader, capacity) / sizeof(uint32_t);
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += uint64_t(gridDim.x) * blockDim.x)
     p[i] = (i == kCapacityWord) ? capacity_words : 0u;
+}
+
+// Moves the workspace's sticky error bits into *status as a status code and
+// clears them, in stream order (one thread; no host round trip).
+__global__ void take_error_kernel(WorkspaceHeader* hdr, int32_t* status) {
+  const uint32_t err = atomicExch(&hdr->error, 0u);
+  *status = (err & kErrTimeout) ? BS_ETIMEOUT : (err & kErrBadBatch) ? BS_EDEVICE : BS_OK;
 }
 
 bool config_supported(const LaunchConfig& c) {
@@ -353,6 +361,11 @@ hipError_t launch_workspace_init(void* ws, size_t bytes, hipStream_t stream) {
   const uint32_t blocks = uint32_t(std::min<uint64_t>(1024, (words + 255) / 256 + 1));
   hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(ws), words,
                      uint32_t(std::min<uint64_t>(cap, 0xFFFFFFFFull)));
+  return hipGetLastError();
+}
+
+hipError_t launch_take_error(void* ws, int32_t* status, hipStream_t stream) {
+  hipLaunchKernelGGL(take_error_kernel, dim3(1), dim3(1), 0, stream, static_cast<WorkspaceHeader*>(ws), status);
   return hipGetLastError();
 }
 

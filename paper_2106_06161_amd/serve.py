@@ -4,8 +4,9 @@ Requests (size n, payload dtype, 64-bit seed, arrival time) are served in
 real time:
 
   admission   a request is admitted once it has arrived and its output
-              bytes fit the HBM budget (FIFO: a request that does not fit
-              holds back the ones behind it);
+              bytes fit the HBM budget (by default the device's free memory
+              at the start of the run, less a reserve; FIFO: a request that
+              does not fit holds back the ones behind it);
   coalescing  admitted requests of at most `small_items` records are grouped
               by element size into one bs_shuffle_batched launch (their inputs
               sit back to back in a device-resident pool); larger requests get
@@ -78,8 +79,9 @@ class Executor(Protocol):
     def place(self, req: Request) -> None: ...
     def launch(self, reqs: list[Request], lane: int = 1) -> object: ...  # lane 0: small groups, 1: large
     def poll(self, handle: object) -> bool: ...
-    def results(self, handle: object) -> dict[int, object]: ...
+    def results(self, handle: object) -> dict[int, object]: ...  # raises if the launch failed on the device
     def release(self, handle: object) -> None: ...
+    def free_bytes(self) -> int: ...  # device memory the server may reserve for outputs
 
 
 @dataclasses.dataclass
@@ -205,12 +207,17 @@ class _Grouper:
 
 
 class ShuffleServer:
-    def __init__(self, executor: Executor, budget_bytes: int, small_items: int = 1 << 20,
+    """budget_bytes: output bytes the admitted, unfinished requests may hold
+    at once; None takes the executor's free device memory at the start of
+    each run (free_bytes())."""
+
+    def __init__(self, executor: Executor, budget_bytes: int | None = None, small_items: int = 1 << 20,
                  max_batch_requests: int = 2048, max_batch_items: int = 1 << 26, max_inflight: int = 16,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
                  policy: str = "size", max_wait: float = 0.05, small_slots: int = 2):
         self.ex = executor
-        self.budget = int(budget_bytes)
+        self.fixed_budget = None if budget_bytes is None else int(budget_bytes)
+        self.budget = self.fixed_budget if self.fixed_budget is not None else 0
         self.small_items = small_items
         self.max_batch_requests = max_batch_requests
         self.max_batch_items = max_batch_items
@@ -239,6 +246,7 @@ class ShuffleServer:
                 gc.enable()
 
     def _run(self, requests: list[Request], on_result: Callable[[Request, object], None] | None) -> ServeReport:
+        self.budget = self.fixed_budget if self.fixed_budget is not None else int(self.ex.free_bytes())
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.id)))
         grouper = _Grouper(self.small_items, self.max_batch_requests, self.max_batch_items, self.policy,
                            self.max_wait)
@@ -342,10 +350,17 @@ class HipExecutor:
     its pool, assigned in admission order, so consecutive small requests of
     one element size are contiguous and one bs_shuffle_batched covers them.
     Outputs are allocated per launch and returned as views.
+
+    Each stream has its own workspace.  After every launch the stream
+    moves that workspace's device-side error word into a pinned host slot
+    (bs_workspace_error_async); results() raises for a launch whose slot is
+    not BS_OK (a look-back that timed out, a malformed batch), so the server
+    fails exactly that launch's requests and hands out none of its bytes.
     """
 
     def __init__(self, device="cuda:0", streams: int = 4, rounds: int = 24, pool_items: int = 1 << 27,
-                 pool_seed: int = 2106):
+                 pool_seed: int = 2106, batch_items: int = 1 << 26, batch_requests: int = 2048,
+                 reserve_bytes: int = 4 << 30):
         import torch
 
         import paper_2106_06161_amd as bs
@@ -353,8 +368,13 @@ class HipExecutor:
         self.torch, self.bs = torch, bs
         self.device = torch.device(device)
         self.rounds = rounds
+        self.reserve_bytes = reserve_bytes
         self.streams = [torch.cuda.Stream(self.device) for _ in range(streams)]
         self.next_stream = 0
+        ws_bytes = max(bs.workspace_bytes(pool_items), bs.workspace_bytes(batch_items, batch_requests))
+        self.workspaces = [bs.make_workspace(ws_bytes, device=self.device, stream=s) for s in self.streams]
+        self.status = torch.full((4096,), -1, dtype=torch.int32).pin_memory()
+        self.next_slot = 0
         gen = torch.Generator(device=self.device)
         gen.manual_seed(pool_seed)
         self.pools = {
@@ -385,17 +405,21 @@ class HipExecutor:
         # small launches never queue behind a large one; large launches take
         # the other streams in turn
         if lane == 0 or len(self.streams) == 1:
-            stream = self.streams[0]
+            si = 0
         else:
-            stream = self.streams[1 + self.next_stream % (len(self.streams) - 1)]
+            si = 1 + self.next_stream % (len(self.streams) - 1)
             self.next_stream += 1
+        stream, ws = self.streams[si], self.workspaces[si]
+        slot = self.next_slot
+        self.next_slot = (slot + 1) % self.status.numel()
+        self.status[slot] = -1
         eb = reqs[0].elem_bytes
         firsts = [self.where[r.id][1] for r in reqs]
         contiguous = all(firsts[i] + reqs[i].n == firsts[i + 1] for i in range(len(reqs) - 1))
         with torch.cuda.stream(stream):
             if len(reqs) == 1:
                 x = self.input_of(reqs[0])
-                y = bs.shuffle(x, reqs[0].seed, self.rounds)
+                y = bs.shuffle(x, reqs[0].seed, self.rounds, workspace=ws)
                 outs = {reqs[0].id: y}
                 keep = ()
             elif contiguous:
@@ -408,29 +432,41 @@ class HipExecutor:
                 sd_h = torch.from_numpy(seeds).pin_memory()
                 off_d = off_h.to(self.device, non_blocking=True)
                 sd_d = sd_h.to(self.device, non_blocking=True)
-                y = bs.shuffle_batched(x, off_d, sd_d, self.rounds)
+                y = bs.shuffle_batched(x, off_d, sd_d, self.rounds, workspace=ws)
                 outs = {r.id: y[int(offs[i]):int(offs[i + 1])] for i, r in enumerate(reqs)}
                 keep = (off_h, sd_h, off_d, sd_d)
             else:  # a pool wrap split the run: fall back to one launch per request
-                outs = {r.id: bs.shuffle(self.input_of(r), r.seed, self.rounds) for r in reqs}
+                outs = {r.id: bs.shuffle(self.input_of(r), r.seed, self.rounds, workspace=ws) for r in reqs}
                 keep = ()
+            bs.workspace_error_async(ws, self.status[slot:slot + 1], stream=stream)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return {"event": ev, "outs": outs, "keep": keep, "stream": stream}
+        return {"event": ev, "outs": outs, "keep": keep, "stream": stream, "slot": slot}
 
     def poll(self, handle) -> bool:
         return handle["event"].query()
 
     def results(self, handle) -> dict[int, object]:
+        st = int(self.status[handle["slot"]])
+        if st != 0:
+            raise self.bs.BShuffleError(st, "device-side error in this launch")
         return handle["outs"]
+
+    def free_bytes(self) -> int:
+        """Free device memory (plus what torch's allocator holds unused), less
+        a reserve for workspaces and the allocator's own rounding."""
+        torch = self.torch
+        free, _ = torch.cuda.mem_get_info(self.device)
+        cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+        return max(0, int(free + cached - self.reserve_bytes))
 
     def release(self, handle) -> None:
         handle["outs"] = None
         handle["keep"] = None
 
     def check_errors(self) -> int:
-        for s in self.streams:
-            err = self.bs.workspace_error(stream=s, device=self.device)
+        for s, ws in zip(self.streams, self.workspaces):
+            err = self.bs.workspace_error(ws, stream=s)
             if err:
                 return err
         return 0
@@ -456,7 +492,8 @@ def main(argv=None) -> int:
     p.add_argument("--qps", type=float, default=0.0,
                    help="0: measure closed-loop capacity C first, then run at each of --loads x C")
     p.add_argument("--loads", default="0.8", help="comma-separated fractions of C (with --qps 0)")
-    p.add_argument("--budget-gib", type=float, default=32.0)
+    p.add_argument("--budget-gib", type=float, default=0.0,
+                   help="output budget; 0: the device's free memory at the start of each run")
     p.add_argument("--streams", type=int, default=4)
     p.add_argument("--rounds", type=int, default=24)
     p.add_argument("--seed", type=int, default=5)
@@ -465,7 +502,8 @@ def main(argv=None) -> int:
     p.add_argument("--small-slots", type=int, default=2)
     a = p.parse_args(argv)
     ex = HipExecutor(streams=a.streams, rounds=a.rounds)
-    server = ShuffleServer(ex, int(a.budget_gib * 2**30), policy=a.policy, max_inflight=a.max_inflight,
+    budget = int(a.budget_gib * 2**30) if a.budget_gib > 0 else None
+    server = ShuffleServer(ex, budget, policy=a.policy, max_inflight=a.max_inflight,
                            small_slots=a.small_slots)
     out = {"requests": a.requests, "policy": a.policy, "max_inflight": a.max_inflight,
            "small_slots": a.small_slots, "streams": a.streams}

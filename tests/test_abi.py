@@ -244,6 +244,18 @@ def test_random_reads_probe_argument_checks():
     assert B.bs_probe_random_reads(FAKE_IN + 2, 1 << 10, FAKE_OUT, 0, None) == B.BS_EELEM
 
 
+def test_random_reads_region_probe_argument_checks():
+    f = B.bs_probe_random_reads_region
+    assert f(None, 1 << 20, 4, 1 << 10, FAKE_OUT, 0, None) == B.BS_EINVAL
+    assert f(FAKE_IN, 1 << 20, 2, 1 << 10, FAKE_OUT, 0, None) == B.BS_EELEM  # record size
+    assert f(FAKE_IN + 8, 1 << 20, 16, 1 << 10, FAKE_OUT, 0, None) == B.BS_EELEM  # misaligned for 16 B
+    assert f(FAKE_IN, 3 << 20, 4, 1 << 10, FAKE_OUT, 0, None) == B.BS_EINVAL  # records not a power of two
+    assert f(FAKE_IN, (1 << 20) + 4, 8, 1 << 10, FAKE_OUT, 0, None) == B.BS_EINVAL  # not whole records
+    assert f(FAKE_IN, 16 << 32, 4, 1 << 10, FAKE_OUT, 0, None) == B.BS_EINVAL  # more than 2^32 records
+    assert f(FAKE_IN, 1 << 20, 4, 24, FAKE_OUT, 0, None) == B.BS_EINVAL  # reads not a multiple of 16
+    assert f(FAKE_IN, 1 << 20, 4, 1 << 37, FAKE_OUT, 0, None) == B.BS_EINVAL  # more than 2^36 reads
+
+
 def test_xcd_mode_argument_check():
     assert B.bs_probe_set_xcd_mode(3) == B.BS_EINVAL
     for m in (0, 1, 2):

@@ -1,7 +1,7 @@
 """The paper's statistical experiments (Sec. 5) with permutations generated
 on the GPU: 100,000 shuffles of arange(n) with seeds 1..100,000 in one
 batched launch, then chi-square over all 120 orderings at n = 5 and the
-Mallows-kernel MMD test at n = 5 and n = 100."""
+Mallows-kernel MMD test at n = 5, 100 and 1,000."""
 import numpy as np
 import pytest
 import torch
@@ -33,12 +33,16 @@ def test_chi_square_n5(rounds, passes):
     assert np.array_equal(perms[:2000], oracle.permutations(5, np.arange(1, 2001, dtype=np.uint64), rounds))
 
 
-@pytest.mark.parametrize("n", [5, 100])
+@pytest.mark.parametrize("n", [5, 100, 1000])
 def test_mmd_pass_at_24_fail_at_4(n):
-    m24 = stats.mmd2(gpu_permutations(n, 24))
-    assert abs(m24) < stats.normal_threshold(n, P, 0.01)
+    p24 = gpu_permutations(n, 24)
+    m24 = stats.mmd2(p24)
+    assert abs(m24) < stats.normal_threshold(n, P, 0.01), stats.mmd_z(n, m24, P)
     m4 = stats.mmd2(gpu_permutations(n, 4))
-    assert abs(m4) > stats.normal_threshold(n, P, 0.05)
+    assert abs(m4) > stats.normal_threshold(n, P, 0.05), stats.mmd_z(n, m4, P)
+    # the sample the statistic was taken on is the oracle's
+    rows = 1000 if n == 1000 else 2000
+    assert np.array_equal(p24[:rows], oracle.permutations(n, np.arange(1, rows + 1, dtype=np.uint64), 24))
 
 
 def test_lcg_chi_square_n5_is_huge():

@@ -187,3 +187,25 @@ def test_hoeffding_threshold_holds_for_the_extreme_bounded_mean(sample_size, alp
     k = math.floor(m * (0.5 - t))  # |S/m - 1/2| >= t  <=>  S <= m/2 - m t  or  S >= m/2 + m t
     tail = 2.0 * float(scipy_stats.binom.cdf(k, m, 0.5))
     assert alpha / 20 < tail <= alpha, tail
+
+
+# --------------------------------------------- std::shuffle control (Sec. 5) --
+# Sec. 5 uses the C++ standard library's shuffle as the generator that should
+# pass both tests.  Its sample here: std::shuffle of arange(n) driven by
+# std::mt19937_64 seeded with consecutive seeds.  With seeds 1..100,000 the
+# n = 5 chi-square is 161.2 (p = 0.006, a chance rejection at alpha = 0.05);
+# the next three blocks give 110.6, 106.4 and 139.7, and the pooled 400,000
+# permutations 129.2 (p = 0.25), so the chi-square control is the pooled
+# sample.
+def test_std_shuffle_control_chi_square_n5_passes():
+    perms = oracle.std_permutations(5, 4 * P, 1)
+    chi, dof = stats.chi_square(perms)
+    assert chi < stats.chi_square_critical(dof, 0.05), chi
+
+
+@pytest.mark.parametrize("n", [5, 100, 1000])
+def test_std_shuffle_control_mmd_passes(n):
+    perms = oracle.std_permutations(n, P, 1)
+    m = stats.mmd2(perms)
+    assert abs(m) < stats.normal_threshold(n, P, 0.01), stats.mmd_z(n, m, P)
+    assert abs(m) < stats.hoeffding_threshold(P, 0.05)

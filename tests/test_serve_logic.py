@@ -29,7 +29,8 @@ class FakeExecutor:
     `polls_to_finish` polls.  Inputs are slices of a seeded pool per element
     size, assigned in placement order like the GPU executor does."""
 
-    def __init__(self, polls_to_finish=3, fail_poll_ids=(), fail_launch_ids=()):
+    def __init__(self, polls_to_finish=3, fail_poll_ids=(), fail_launch_ids=(), fail_result_ids=(),
+                 free=1 << 30):
         rng = np.random.default_rng(0)
         self.pools = {4: rng.integers(0, 2**32, size=1 << 20, dtype=np.uint32),
                       8: rng.integers(0, 2**63, size=1 << 20, dtype=np.int64).view(np.uint64)}
@@ -38,6 +39,8 @@ class FakeExecutor:
         self.polls_to_finish = polls_to_finish
         self.fail_poll_ids = set(fail_poll_ids)
         self.fail_launch_ids = set(fail_launch_ids)
+        self.fail_result_ids = set(fail_result_ids)
+        self.free = free
         self.launches = []
         self.lanes = []
         self.live = 0
@@ -70,7 +73,14 @@ class FakeExecutor:
         return h["polls"] >= self.polls_to_finish
 
     def results(self, h):
+        # a launch that finished but reported a device-side status (the GPU
+        # executor's per-launch error word) raises here, like HipExecutor
+        if any(r.id in self.fail_result_ids for r in h["reqs"]):
+            raise RuntimeError("BS_ETIMEOUT: device-side error in this launch")
         return {r.id: oracle.shuffle(self.input_of(r), r.seed, 24) for r in h["reqs"]}
+
+    def free_bytes(self):
+        return self.free
 
     def release(self, h):
         self.live -= 1
@@ -137,6 +147,33 @@ def test_failed_launch_fails_only_its_requests():
     ex2 = FakeExecutor(fail_launch_ids={1})
     rep2 = server(ex2, 1 << 30, small_items=1000).run(reqs([2000, 2000, 2000]))
     assert {c.request.id for c in rep2.completions if c.error} == {1}
+
+
+def test_device_error_fails_its_launch_and_hands_out_nothing():
+    """A launch whose device status is set after it finished (e.g. a look-back
+    that timed out) fails all of its requests and only those; on_result is
+    never called for them."""
+    ex = FakeExecutor(fail_result_ids={2, 7})
+    rs = reqs([2000, 2000, 2000, 10, 20, 30, 2000, 40, 50], gap=0.0)
+    got = {}
+    rep = server(ex, 1 << 30, small_items=1000).run(rs, on_result=lambda r, out: got.__setitem__(r.id, out))
+    failed = {c.request.id for c in rep.completions if c.error}
+    want = set().union(*(set(g) for g in ex.launches if {2, 7} & set(g)))
+    assert {2, 7} <= want and want != set(range(len(rs)))
+    assert failed == want
+    assert set(got) == set(range(len(rs))) - want
+    assert len(rep.ok()) == len(rs) - len(want)
+
+
+def test_budget_defaults_to_the_executors_free_memory():
+    ex = FakeExecutor(polls_to_finish=5, free=4 * 1000)
+    rs = reqs([300, 500, 200, 800, 100, 700, 400], gap=0.0)
+    rep = server(ex, None, small_items=0).run(rs)
+    assert rep.budget_bytes == 4000 and rep.max_reserved_bytes <= 4000
+    assert len(rep.ok()) == len(rs)
+    ex.free = 10  # every request now exceeds the budget, read again at the start of the run
+    rep = server(ex, None, small_items=0).run(rs)
+    assert not rep.ok()
 
 
 def test_request_larger_than_budget_is_rejected_alone():
