@@ -101,6 +101,10 @@ def parse_args():
     p.add_argument("--profile-footprint", action="store_true",
                    help="profiler run: a copy of known size, then the random-read probe over every footprint and "
                         "record size; no extras")
+    p.add_argument("--profile-staged", action="store_true",
+                   help="profiler run: a copy of known size, then --steps staged shuffles of the headline workload "
+                        "(and of n = 10^9 uint32 with --staged-large); no extras")
+    p.add_argument("--staged-large", action="store_true")
     p.add_argument("--profile-large", action="store_true",
                    help="profiler run: a copy of known size, then the large workloads (10^9 uint32, 2.5e8 x 16 B) "
                         "and the u64 n = 2^27+1 shuffle, --steps each; no extras")
@@ -436,6 +440,16 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None,
     t = timer.run(lcg, 5)
     res["lcg_fused_ms"] = t * 1e3
     res["lcg_fused_Gelem_s"] = n / t / 1e9
+    # the staged form: the same output through streaming passes
+    need = bs.staged_scratch_bytes(n, 4)
+    if need:
+        st_scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+        t = timer.run(lambda: bs.shuffle_staged(x, SEED, rounds, out=y, scratch=st_scratch), 5)
+        res["staged_ms"] = t * 1e3
+        res["staged_Gelem_s"] = n / t / 1e9
+        if not torch.equal(y, ref):
+            raise RuntimeError(f"the staged form differs from the fused kernel at n={n}")
+        del st_scratch
     # the index-output and inverse variants: the permutation itself (4-byte
     # indices, coalesced writes) and the un-shuffle in its two forms
     # (coalesced reads and scattered writes through f; coalesced writes and
@@ -558,7 +572,14 @@ def bench_large(torch, bs, B, dev, stream, timer, rounds) -> dict:
     res["u32_1e9_alg_GBps"] = 8.0 * n / t / 1e9
     res["u32_1e9_pct_of_same_footprint_ceiling"] = 100.0 * res["u32_1e9_Gelem_s"] / res["ceiling_u32_4GiB_G_reads_s"]
     res["u32_1e9_launch"] = list(B.bs_query_config(0, 4, n))
-    del x, y
+    st_scratch = torch.empty(bs.staged_scratch_bytes(n, 4), dtype=torch.uint8, device=dev)
+    ref = y.clone()
+    t = timer.run(lambda: bs.shuffle_staged(x, 1, rounds, out=y, scratch=st_scratch), 3)
+    if not torch.equal(y, ref):
+        raise RuntimeError("the staged form differs from the fused kernel at n=10^9")
+    res["u32_1e9_staged_ms"] = t * 1e3
+    res["u32_1e9_staged_Gelem_s"] = n / t / 1e9
+    del x, y, ref, st_scratch
     n = 250_000_000
     gen = torch.Generator(device=dev).manual_seed(11)
     x = torch.randn((n, 4), dtype=torch.float32, device=dev, generator=gen)
@@ -570,7 +591,14 @@ def bench_large(torch, bs, B, dev, stream, timer, rounds) -> dict:
     res["rec16_2p5e8_pct_of_same_footprint_ceiling"] = (100.0 * res["rec16_2p5e8_Gelem_s"]
                                                        / res["ceiling_rec16_4GiB_G_reads_s"])
     res["rec16_2p5e8_launch"] = list(B.bs_query_config(0, 16, n))
-    del x, y
+    st_scratch = torch.empty(bs.staged_scratch_bytes(n, 16), dtype=torch.uint8, device=dev)
+    ref = y.clone()
+    t = timer.run(lambda: bs.shuffle_staged(x, 11, rounds, out=y, scratch=st_scratch), 3)
+    if not torch.equal(y, ref):
+        raise RuntimeError("the staged form differs from the fused kernel at 2.5e8 x 16 B")
+    res["rec16_2p5e8_staged_ms"] = t * 1e3
+    res["rec16_2p5e8_staged_Gelem_s"] = n / t / 1e9
+    del x, y, ref, st_scratch
     if bs.workspace_error(ws) != 0:
         raise RuntimeError("device-side error in the large workloads")
     return res
@@ -714,6 +742,18 @@ def main() -> int:
             res[name] = list(B.bs_query_config(0, x.element_size() * (x.numel() // n), n))
             del x, y, ws
         print(json.dumps({"launch": res}), flush=True)
+        return 0
+
+    if args.profile_staged:
+        n = 10**9 if args.staged_large else N_HEADLINE
+        x = torch.from_numpy(W.uniform_u32(n, seed=SEED)).to(dev)
+        y = torch.empty_like(x)
+        B._check(B.bs_probe_copy(x.data_ptr(), y.data_ptr(), (N_HEADLINE * 4) // 16 * 16, sp), "bs_probe_copy")
+        scratch = torch.empty(bs.staged_scratch_bytes(n, 4), dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup + args.steps):
+            bs.shuffle_staged(x, SEED, rounds, out=y, scratch=scratch)
+        torch.cuda.synchronize()
+        log(f"bench: {args.warmup + args.steps} staged shuffles of n={n}")
         return 0
 
     log("bench: generating the headline input (n=2^27+1 uint32, PCG64 seed 7)")

@@ -231,6 +231,36 @@ bs_status bs_unshuffle_inverse(const void *in, void *out, uint64_t n, uint32_t e
                                uint32_t rounds, void *scratch, size_t scratch_bytes, void *stream);
 
 /*
+ * bs_shuffle_staged -- exactly bs_shuffle's output, out[rank(i)] = in[f(i)],
+ * computed by streaming passes instead of random gathers.  Algorithm 1 seen
+ * from the input side sends record y < n to position rank(f^-1(y)), f^-1
+ * being the inverse cipher (Sec. 3.2).  The input is read in order; each
+ * record goes with its padded index i = f^-1(y) into buckets by the high bits
+ * of i (one or two distribution passes through LDS, whole cache lines to and
+ * from memory); one workgroup per window of 2^s consecutive padded indices
+ * then places the window's records by rank (a popcount over the window's
+ * kept indices plus the kept count of earlier windows) and writes them in
+ * order.  Memory traffic per record: about 2 * (elem_bytes + 4) bytes per
+ * distribution pass plus elem_bytes + 4 to read a window and elem_bytes to
+ * write it, against one random line fill per record in bs_shuffle.
+ *
+ *   scratch  device memory of at least bs_staged_scratch_bytes(n, elem_bytes)
+ *            bytes, 256-byte aligned, overlapping neither in nor out: about
+ *            2 * 2^k * (elem_bytes + 4) bytes for the padded domain 2^k (one
+ *            bucket array per distribution pass, each with room for every
+ *            padded index so no bucket can overflow).  Contents on entry do
+ *            not matter.  NULL or misaligned: BS_EINVAL; too small: BS_ENOMEM;
+ *            overlapping in or out: BS_EALIAS.
+ * Covers padded domains up to 2^32 (and elem_bytes 16 up to 2^30, 8 up to
+ * 2^31): bs_staged_scratch_bytes returns 0 and bs_shuffle_staged BS_EINVAL
+ * outside them.  Other arguments and errors as for bs_shuffle; there is no
+ * look-back (the passes are ordered by the stream) and no workspace.
+ */
+size_t bs_staged_scratch_bytes(uint64_t n, uint32_t elem_bytes);
+bs_status bs_shuffle_staged(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                            uint32_t rounds, void *scratch, size_t scratch_bytes, void *stream);
+
+/*
  * The linear congruential bijection of Sec. 3.1 as the shuffle's f, for
  * comparison with VariablePhilox (Sec. 5 reports its poor quality: at n = 5
  * its chi-square statistic is in the hundreds of thousands).

@@ -30,10 +30,13 @@ from .binding import (  # noqa: F401
     shuffle,
     shuffle_batched,
     shuffle_lcg,
+    shuffle_staged,
+    staged_scratch_bytes,
     unshuffle,
     unshuffle_inverse,
     workspace_bytes,
     workspace_error,
+    workspace_error_async,
 )
 
 __version__ = "0.1.0"

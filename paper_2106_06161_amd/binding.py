@@ -60,6 +60,8 @@ _SIGNATURES = {
     "bs_bijection": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _u32, _vp]),
     "bs_unshuffle_inverse_scratch_bytes": (_sz, [_u64]),
     "bs_unshuffle_inverse": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
+    "bs_staged_scratch_bytes": (_sz, [_u64, _u32]),
+    "bs_shuffle_staged": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32, _u32]),
     "bs_load_tuned_configs": (_i32, [ctypes.c_char_p]),
     "bs_save_tuned_configs": (_i32, [ctypes.c_char_p]),
@@ -502,3 +504,45 @@ def workspace_error_async(workspace, status, stream=None) -> None:
     with torch.cuda.device(workspace.device):
         _check(lib().bs_workspace_error_async(workspace.data_ptr(), status.data_ptr(), sp),
                "bs_workspace_error_async")
+
+
+def bs_staged_scratch_bytes(n: int, elem_bytes: int) -> int:
+    return int(lib().bs_staged_scratch_bytes(n, elem_bytes))
+
+
+def bs_shuffle_staged(in_ptr, out_ptr, n, elem_bytes, seed, rounds, scratch, scratch_bytes, stream) -> int:
+    return int(lib().bs_shuffle_staged(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, scratch,
+                                       scratch_bytes, stream))
+
+
+def staged_scratch_bytes(n: int, elem_bytes: int) -> int:
+    """Scratch bytes bs_shuffle_staged needs (0: the staged form does not cover this size)."""
+    return bs_staged_scratch_bytes(n, elem_bytes)
+
+
+def shuffle_staged(x, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, scratch=None, stream=None):
+    """bs_shuffle's result through the staged (streaming) passes; scratch is a
+    uint8 GPU tensor of at least staged_scratch_bytes(n, elem_bytes) bytes
+    (allocated here when None)."""
+    import torch
+
+    _require_device(x, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    _require_device(out, "out")
+    if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype and device")
+    n, eb = _records(x)
+    if n == 0:
+        return out
+    need = bs_staged_scratch_bytes(n, eb)
+    if need == 0:
+        raise BShuffleError(BS_EINVAL, "bs_shuffle_staged: size outside the staged form")
+    if scratch is None:
+        scratch = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _require_device(scratch, "scratch")
+    with torch.cuda.device(x.device):
+        st = bs_shuffle_staged(x.data_ptr(), out.data_ptr(), n, eb, seed, rounds, scratch.data_ptr(),
+                               scratch.numel() * scratch.element_size(), _stream_ptr(x, stream))
+    _check(st, "bs_shuffle_staged")
+    return out

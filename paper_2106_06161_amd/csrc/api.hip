@@ -811,3 +811,80 @@ extern "C" bs_status bs_unshuffle_inverse(const void* in, void* out, uint64_t n,
   const hipError_t e = bsd::launch_unshuffle_inverse(a, elem_bytes, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? BS_OK : hip_fail(e);
 }
+
+namespace {
+
+struct StagedLayout {
+  bool ok = false;
+  uint32_t k = 0, s = 0, b1 = 0, b2 = 0;
+  size_t cnt_a = 0, cnt_b = 0, base_b = 0, idx_a = 0, val_a = 0, idx_b = 0, val_b = 0, total = 0;
+};
+
+// Scratch of the staged form: counts, the window prefix, then the two bucket
+// arrays (index and record arrays each; the first pass's arrays only when
+// there are two distribution passes), every part 256-byte aligned.
+StagedLayout staged_layout(uint64_t n, uint32_t elem_bytes) {
+  StagedLayout l;
+  if (!valid_elem_bytes(elem_bytes) || n == 0 || n > BS_MAX_ITEMS) return l;
+  l.k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
+  if (!bsd::staged_digits(l.k, elem_bytes, &l.s, &l.b1, &l.b2)) return l;
+  const uint64_t domain = uint64_t(1) << l.k;
+  const uint64_t windows = uint64_t(1) << (l.b1 + l.b2);
+  l.cnt_a = 0;
+  l.cnt_b = l.cnt_a + align256((uint64_t(1) << l.b1) * 4);
+  l.base_b = l.cnt_b + align256(windows * 4);
+  l.idx_a = l.base_b + align256(windows * 4);
+  l.val_a = l.idx_a + (l.b2 ? align256(domain * 4) : 0);
+  l.idx_b = l.val_a + (l.b2 ? align256(domain * elem_bytes) : 0);
+  l.val_b = l.idx_b + align256(domain * 4);
+  l.total = l.val_b + align256(domain * elem_bytes);
+  l.ok = true;
+  return l;
+}
+
+}  // namespace
+
+extern "C" size_t bs_staged_scratch_bytes(uint64_t n, uint32_t elem_bytes) {
+  const StagedLayout l = staged_layout(n, elem_bytes);
+  return l.ok ? l.total : 0;
+}
+
+extern "C" bs_status bs_shuffle_staged(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                       uint32_t rounds, void* scratch, size_t scratch_bytes, void* stream) {
+  const bs_status st = check_single_args(in, out, n, elem_bytes, rounds);
+  if (st != BS_OK || n == 0) return st;
+  const StagedLayout l = staged_layout(n, elem_bytes);
+  if (!l.ok) return BS_EINVAL;
+  if (!scratch || reinterpret_cast<uintptr_t>(scratch) % 256) return BS_EINVAL;
+  if (scratch_bytes < l.total) return BS_ENOMEM;
+  {
+    // [scratch, scratch + total) against [in, in + n*eb) and [out, out + n*eb)
+    const uintptr_t sc = reinterpret_cast<uintptr_t>(scratch);
+    const uintptr_t x = reinterpret_cast<uintptr_t>(in), y = reinterpret_cast<uintptr_t>(out);
+    const uint64_t bytes = n * elem_bytes;
+    if ((sc < x + bytes && x < sc + l.total) || (sc < y + bytes && y < sc + l.total)) return BS_EALIAS;
+  }
+  bsd::SingleArgs c = {};
+  setup_cipher(c, n, seed, rounds);
+  bsd::StagedArgs a = {};
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  a.n = n;
+  a.cs = c.cs;
+  a.k = l.k;
+  a.rounds = rounds;
+  a.s = l.s;
+  a.b1 = l.b1;
+  a.b2 = l.b2;
+  uint8_t* base = static_cast<uint8_t*>(scratch);
+  a.cnt_a = reinterpret_cast<uint32_t*>(base + l.cnt_a);
+  a.cnt_b = reinterpret_cast<uint32_t*>(base + l.cnt_b);
+  a.base_b = reinterpret_cast<uint32_t*>(base + l.base_b);
+  a.idx_a = reinterpret_cast<uint32_t*>(base + l.idx_a);
+  a.val_a = base + l.val_a;
+  a.idx_b = reinterpret_cast<uint32_t*>(base + l.idx_b);
+  a.val_b = base + l.val_b;
+  std::copy(std::begin(c.key), std::end(c.key), std::begin(a.key));
+  const hipError_t e = bsd::launch_staged(a, elem_bytes, 0, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}

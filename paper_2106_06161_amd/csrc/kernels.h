@@ -105,6 +105,29 @@ struct BijectionArgs {
   uint32_t key[kMaxRounds + 1];  // round keys masked to the half width, then 0
 };
 
+// Staged form (streaming passes; see staged.hip): bucket arrays in the
+// caller's scratch.  Pass-1 buckets: 2^b1 regions of 2^(k - b1) entries;
+// windows: 2^(b1 + b2) regions of 2^s entries; each entry is a padded index
+// (idx) and a record (val), in two arrays.
+struct StagedArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  uint64_t n;
+  CipherShape cs;
+  uint32_t k;       // domain bits
+  uint32_t rounds;
+  uint32_t s;       // window bits
+  uint32_t b1, b2;  // digit bits of the first and second distribution passes (b2 = 0: one pass)
+  uint32_t* idx_a;
+  uint8_t* val_a;
+  uint32_t* cnt_a;   // 2^b1 bucket counts
+  uint32_t* idx_b;
+  uint8_t* val_b;
+  uint32_t* cnt_b;   // 2^(b1 + b2) window counts
+  uint32_t* base_b;  // exclusive prefix of cnt_b
+  uint32_t key[kMaxRounds + 1];  // round keys masked to the half width, then 0
+};
+
 struct LaunchConfig {
   uint32_t waves;      // wavefronts per workgroup
   uint32_t items;      // indices per lane per tile
@@ -131,6 +154,9 @@ hipError_t launch_tile_prefix(const uint64_t* counts, uint64_t* prefix, uint32_t
 hipError_t launch_cipher_table(const SingleArgs& a, uint32_t* table, hipStream_t stream);
 hipError_t launch_bijection(const BijectionArgs& a, hipStream_t stream);
 hipError_t launch_unshuffle_inverse(const InverseArgs& a, uint32_t elem_bytes, hipStream_t stream);
+uint32_t staged_window_bits(uint32_t elem_bytes);
+bool staged_digits(uint32_t k, uint32_t elem_bytes, uint32_t* s, uint32_t* b1, uint32_t* b2);
+hipError_t launch_staged(const StagedArgs& a, uint32_t elem_bytes, uint32_t num_cus, hipStream_t stream);
 
 bool config_supported(const LaunchConfig& cfg);
 // The shape a batched launch runs: cfg when compiled, else the default

@@ -54,3 +54,18 @@ def check_slices(x_np: np.ndarray, y_np: np.ndarray, seed: int, rounds: int, sta
         want = oracle.shuffle_window(x_np, seed, rounds, s, s + span)
         got = y_np[rank:rank + len(want)]
         assert np.array_equal(got, want), (n, s)
+
+
+def oracle_whole(x_np: np.ndarray, seed: int, rounds: int, chunks: int = 64) -> np.ndarray:
+    """The oracle's whole output, its padded domain split into `chunks`
+    consecutive windows run on parallel threads and concatenated in order
+    (each window's outputs are the ranks that follow the previous window's)."""
+    n = x_np.shape[0]
+    domain = 1 << oracle.domain_bits(n)
+    bounds = np.linspace(0, domain, chunks + 1, dtype=np.int64)
+    with concurrent.futures.ThreadPoolExecutor(THREADS) as ex:
+        parts = list(ex.map(lambda ab: oracle.shuffle_window(x_np, seed, rounds, int(ab[0]), int(ab[1])),
+                            zip(bounds[:-1], bounds[1:])))
+    out = np.concatenate(parts)
+    assert out.shape[0] == n
+    return out

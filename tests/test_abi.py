@@ -317,3 +317,24 @@ def test_noalloc_argument_checks():
     assert B.bs_shuffle_noalloc(FAKE_IN, FAKE_IN, 10, 4, 1, 24, None) == B.BS_EALIAS
     assert B.bs_shuffle_noalloc(FAKE_IN, FAKE_OUT, B.NOALLOC_MAX_ITEMS + 1, 4, 1, 24, None) == B.BS_ENOMEM
 
+
+
+def test_staged_scratch_sizes_and_argument_checks():
+    # n = 2^27 + 1 uint32: k = 28, windows of 2^14, two passes of 7 digit bits
+    want = 512 + 2 * (1 << 16) + 4 * (1 << 30)
+    assert B.bs_staged_scratch_bytes((1 << 27) + 1, 4) == want
+    assert B.bs_staged_scratch_bytes(0, 4) == 0
+    assert B.bs_staged_scratch_bytes(1000, 3) == 0
+    assert B.bs_staged_scratch_bytes((1 << 32) + 1, 4) == 0  # domain above 2^32
+    assert B.bs_staged_scratch_bytes(1 << 31, 8) > 0 and B.bs_staged_scratch_bytes((1 << 31) + 1, 8) == 0
+    n = 1 << 20
+    need = B.bs_staged_scratch_bytes(n, 4)
+    f = B.bs_shuffle_staged
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, None, need, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, 1 << 42, need - 1, None) == B.BS_ENOMEM
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, (1 << 42) + 64, need, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, FAKE_IN - 256, need, None) == B.BS_EALIAS
+    assert f(FAKE_IN, FAKE_OUT, n, 3, 1, 24, 1 << 42, need, None) == B.BS_EELEM
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 65, 1 << 42, need, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, (1 << 32) + 1, 4, 1, 24, 1 << 42, 1 << 40, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, 0, 4, 1, 24, None, 0, None) == B.BS_OK

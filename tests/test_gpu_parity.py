@@ -14,7 +14,7 @@ import oracle
 import paper_2106_06161_amd as bs
 from paper_2106_06161_amd import binding as B
 from paper_2106_06161_amd import workloads as W
-from _helpers import oracle_window
+from _helpers import oracle_whole, oracle_window
 
 pytestmark = pytest.mark.gpu
 
@@ -176,6 +176,14 @@ def test_headline_workload_4_rounds_whole():
     """n = 2^27 + 1 uniform uint32 (seed 7), domain 2^28, 4 rounds: whole output."""
     x = W.uniform_u32((1 << 27) + 1, seed=7)
     assert np.array_equal(gpu(x, 7, 4), oracle.shuffle(x, 7, 4))
+
+
+def test_headline_workload_24_rounds_whole():
+    """The benched configuration itself: n = 2^27 + 1 uniform uint32 (seed 7),
+    domain 2^28, 24 rounds; the whole output against the oracle's (computed
+    over 64 windows of the padded domain on parallel threads)."""
+    x = W.uniform_u32((1 << 27) + 1, seed=7)
+    assert np.array_equal(gpu(x, 7, 24), oracle_whole(x, 7, 24))
 
 
 def test_headline_workload_24_rounds_slices():

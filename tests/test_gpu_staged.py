@@ -1,0 +1,136 @@
+"""bs_shuffle_staged (the streaming-pass form) against the oracle: the same
+output as Algorithm 1 for every record size, both parities of k, one and two
+distribution passes, the single-window case, ragged tails, zero and few
+rounds, repeated calls on one scratch and graph replay; the headline
+workload whole."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2106_06161_amd as bs
+from paper_2106_06161_amd import binding as B
+from paper_2106_06161_amd import workloads as W
+
+from _helpers import oracle_whole
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+NP = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+
+
+def records(n, eb, seed):
+    rng = np.random.default_rng(seed)
+    if eb == 16:
+        return rng.integers(0, 2**63, size=(n, 2), dtype=np.int64)
+    return rng.integers(0, np.iinfo(NP[eb]).max, size=n, dtype=NP[eb], endpoint=True)
+
+
+def to_dev(x_np):
+    if x_np.dtype == np.uint16:
+        return torch.from_numpy(x_np.view(np.int16)).to(DEV)
+    if x_np.dtype == np.uint32:
+        return torch.from_numpy(x_np.view(np.int32)).to(DEV)
+    if x_np.dtype == np.uint64:
+        return torch.from_numpy(x_np.view(np.int64)).to(DEV)
+    return torch.from_numpy(x_np).to(DEV)
+
+
+def staged(x_np, seed, rounds):
+    x = to_dev(x_np)
+    y = bs.shuffle_staged(x, seed, rounds)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().view(x_np.dtype).reshape(x_np.shape)
+
+
+# (n, elem_bytes): single window (k <= s), one pass, the widest one-pass split,
+# two passes; odd and even k; ragged tails
+CASES = [(1, 4), (5, 4), (1000, 4), (4097, 4), (100_000, 4), ((1 << 20) + 1, 4), ((1 << 22) + 3, 4),
+         ((1 << 23) + 1, 4), ((1 << 24) - 5, 4), (70_001, 1), ((1 << 22) + 1, 1), (100_003, 2),
+         ((1 << 23) + 7, 2), (65_537, 8), ((1 << 21) + 1, 8), ((1 << 23) + 1, 8), (3000, 16),
+         ((1 << 20) + 1, 16), ((1 << 22) + 1, 16)]
+
+
+@pytest.mark.parametrize("n,eb", CASES)
+def test_staged_equals_oracle(n, eb):
+    x = records(n, eb, seed=n + eb)
+    assert np.array_equal(staged(x, 1000 + n, 24), oracle.shuffle(x, 1000 + n, 24)), (n, eb)
+
+
+@pytest.mark.parametrize("rounds", [0, 1, 4, 64])
+def test_staged_round_counts(rounds):
+    x = records((1 << 23) + 1, 4, seed=3)
+    assert np.array_equal(staged(x, 9, rounds), oracle.shuffle(x, 9, rounds))
+
+
+def test_staged_splits():
+    """The pass structure the cases above cover."""
+    for n, eb in CASES:
+        assert bs.staged_scratch_bytes(n, eb) > 0
+    assert bs.staged_scratch_bytes((1 << 32) + 1, 4) == 0  # k = 33
+    assert bs.staged_scratch_bytes(1 << 31, 16) == 0  # k = 31 > 12 + 18
+
+
+def test_staged_repeated_calls_and_sizes_on_one_scratch():
+    sizes = [(1 << 23) + 1, 1000, (1 << 22) + 3, 100_000, (1 << 23) + 1]
+    need = max(bs.staged_scratch_bytes(n, 4) for n in sizes)
+    scratch = torch.empty(need, dtype=torch.uint8, device=DEV)
+    for i, n in enumerate(sizes):
+        x_np = records(n, 4, seed=i)
+        x = to_dev(x_np)
+        y = bs.shuffle_staged(x, 50 + i, 24, scratch=scratch)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), oracle.shuffle(x_np, 50 + i, 24)), n
+
+
+def test_staged_under_graph_replay():
+    n = (1 << 23) + 1
+    x_np = records(n, 4, seed=11)
+    want = oracle.shuffle(x_np, 77, 24)
+    x = to_dev(x_np)
+    y = torch.empty_like(x)
+    scratch = torch.empty(bs.staged_scratch_bytes(n, 4), dtype=torch.uint8, device=DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bs.shuffle_staged(x, 77, 24, out=y, scratch=scratch)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        bs.shuffle_staged(x, 77, 24, out=y, scratch=scratch)
+    for rep in range(4):
+        y.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), want), rep
+        bs.shuffle_staged(x[: n // 2], 3, 24, out=y[: n // 2], scratch=scratch)  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_staged_equals_fused_on_the_headline_workload_whole():
+    """n = 2^27 + 1 uniform uint32 (PCG64 seed 7), seed 7, 24 rounds: the
+    whole staged output equals the oracle's and the fused kernel's."""
+    x_np = W.uniform_u32((1 << 27) + 1, seed=7)
+    x = torch.from_numpy(x_np).to(DEV)
+    y = bs.shuffle_staged(x, 7, 24)
+    z = bs.shuffle(x, 7, 24)
+    torch.cuda.synchronize()
+    assert torch.equal(y, z)
+    assert np.array_equal(y.cpu().numpy(), oracle_whole(x_np, 7, 24))
+
+
+def test_staged_argument_errors_on_device():
+    x = torch.zeros(1 << 20, dtype=torch.int32, device=DEV)
+    y = torch.empty_like(x)
+    need = bs.staged_scratch_bytes(1 << 20, 4)
+    small = torch.empty(need - 256, dtype=torch.uint8, device=DEV)
+    sp = torch.cuda.current_stream().cuda_stream
+    assert B.bs_shuffle_staged(x.data_ptr(), y.data_ptr(), 1 << 20, 4, 1, 24, small.data_ptr(), small.numel(),
+                               sp) == B.BS_ENOMEM
+    big = torch.empty(need, dtype=torch.uint8, device=DEV)
+    assert B.bs_shuffle_staged(x.data_ptr(), y.data_ptr(), 1 << 20, 4, 1, 24, big.data_ptr() + 16, need,
+                               sp) == B.BS_EINVAL
+    # scratch overlapping the output
+    assert B.bs_shuffle_staged(x.data_ptr(), big.data_ptr(), 1 << 18, 4, 1, 24, big.data_ptr(), need,
+                               sp) == B.BS_EALIAS
