@@ -240,23 +240,41 @@ bs_status bs_unshuffle_inverse(const void *in, void *out, uint64_t n, uint32_t e
  * from memory); one workgroup per window of 2^s consecutive padded indices
  * then places the window's records by rank (a popcount over the window's
  * kept indices plus the kept count of earlier windows) and writes them in
- * order.  Memory traffic per record: about 2 * (elem_bytes + 4) bytes per
- * distribution pass plus elem_bytes + 4 to read a window and elem_bytes to
- * write it, against one random line fill per record in bs_shuffle.
+ * order.  Memory traffic per record: elem_bytes read and elem_bytes + 4
+ * written by the first pass, elem_bytes + 4 read and elem_bytes + 2 written
+ * by the second, elem_bytes + 2 read and elem_bytes written by the place
+ * pass (6 * elem_bytes + 12 in all; 36 bytes for 4-byte records), every
+ * access part of a whole-line stream, against one random 128-byte line fill
+ * per record in bs_shuffle.
  *
  *   scratch  device memory of at least bs_staged_scratch_bytes(n, elem_bytes)
  *            bytes, 256-byte aligned, overlapping neither in nor out: about
- *            2 * 2^k * (elem_bytes + 4) bytes for the padded domain 2^k (one
+ *            2^k * (2 * elem_bytes + 6) bytes for the padded domain 2^k (one
  *            bucket array per distribution pass, each with room for every
- *            padded index so no bucket can overflow).  Contents on entry do
- *            not matter.  NULL or misaligned: BS_EINVAL; too small: BS_ENOMEM;
- *            overlapping in or out: BS_EALIAS.
+ *            padded index so no bucket can overflow; 4-byte indices in the
+ *            first, 2-byte window indices in the second).  Contents on entry
+ *            do not matter.  NULL or misaligned: BS_EINVAL; too small:
+ *            BS_ENOMEM; overlapping in or out: BS_EALIAS.
  * Covers padded domains up to 2^32 (and elem_bytes 16 up to 2^30, 8 up to
  * 2^31): bs_staged_scratch_bytes returns 0 and bs_shuffle_staged BS_EINVAL
  * outside them.  Other arguments and errors as for bs_shuffle; there is no
  * look-back (the passes are ordered by the stream) and no workspace.
  */
 size_t bs_staged_scratch_bytes(uint64_t n, uint32_t elem_bytes);
+
+/*
+ * bs_workspace_bytes_staged -- a workspace size with which bs_shuffle may take
+ * the staged form: bs_workspace_bytes(n, 0, elem_bytes) rounded up to 256
+ * bytes, plus bs_staged_scratch_bytes(n, elem_bytes) (just the former when
+ * the staged form does not cover n).  bs_shuffle runs the staged form, with
+ * the same output, when its caller-provided workspace is at least this large
+ * and the tuned table prefers the staged form for the call's element size and
+ * domain bits (a "staged" table line; see bs_autotune); otherwise, and always
+ * with the library's own workspace or while a shape is forced with
+ * bs_set_config, it runs the fused kernel.  0 for n > BS_MAX_ITEMS or a bad
+ * elem_bytes.
+ */
+size_t bs_workspace_bytes_staged(uint64_t n, uint32_t elem_bytes);
 bs_status bs_shuffle_staged(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
                             uint32_t rounds, void *scratch, size_t scratch_bytes, void *stream);
 
@@ -318,6 +336,9 @@ bs_status bs_bijection(const uint64_t *in, uint64_t *out, uint64_t count, uint32
 #define BS_GRID_ONE_PER_TILE 1000u
 #define BS_DEPTH_COMPACT 8u
 #define BS_DEPTH_COMPACT_PIPE 9u
+/* bs_query_config's depth for a bs_shuffle that takes the staged form
+ * (bs_shuffle_staged's passes; waves and items are then 0). */
+#define BS_DEPTH_STAGED 16u
 bs_status bs_set_config(uint32_t waves_per_group, uint32_t items_per_lane, uint32_t depth, uint32_t grid_mult);
 bs_status bs_get_config(uint32_t *waves_per_group, uint32_t *items_per_lane, uint32_t *depth,
                         uint32_t *grid_mult);
@@ -359,7 +380,11 @@ bs_status bs_clear_tuned_configs(void);
  * device's architecture when one is available.
  *
  * Format: '#' starts a comment; "arch <name>" and "rounds <r>" lines; one
- * entry per line: kind elem_bytes size_bits waves items depth grid_mult [ms].
+ * entry per line: kind elem_bytes size_bits waves items depth grid_mult [ms],
+ * or "staged elem_bytes size_bits prefer [ms_staged ms_fused]" (prefer = 1:
+ * bs_shuffle takes the staged form for that class when its workspace allows,
+ * see bs_workspace_bytes_staged).  The tuner times the staged form against
+ * the best fused shape for single-shuffle classes of 2^20 indices and up.
  */
 #define BS_AUTOTUNE_VERBOSE 1u
 bs_status bs_autotune(int device, const char *cache_path, uint32_t max_size_bits, uint32_t flags);

@@ -108,6 +108,15 @@ bs_status bs_probe_set_xcd_mode(uint32_t mode);
  */
 bs_status bs_probe_set_batch_small(uint32_t enable);
 
+/*
+ * bs_probe_set_staged_policy -- when bs_shuffle takes the staged form (never
+ * changes results): 0 never, 1 whenever the caller's workspace holds the
+ * staged scratch (bs_workspace_bytes_staged) and the staged form covers n,
+ * 2 (default) as the tuned table prefers.  BS_EINVAL for other values.
+ * Applies to every later call from every thread.
+ */
+bs_status bs_probe_set_staged_policy(uint32_t mode);
+
 /* Selects plain (0) or non-temporal (1) output stores for bs_shuffle. */
 bs_status bs_probe_set_store_mode(uint32_t nontemporal);
 

@@ -24,19 +24,35 @@ KIND_SINGLE, KIND_BATCHED = 0, 1
 
 
 def read_table(path: str = TUNED_FILE) -> list[dict]:
-    """Entries of a table file, as dicts (the library reads the same format)."""
+    """Shape entries of a table file, as dicts (the library reads the same format)."""
     keys = ("kind", "elem_bytes", "size_bits", "waves", "items", "depth", "grid_mult")
     entries = []
     with open(path) as fh:
         for line in fh:
             line = line.split("#", 1)[0].split()
-            if not line or line[0] in ("arch", "rounds"):
+            if not line or line[0] in ("arch", "rounds", "staged"):
                 continue
             e = dict(zip(keys, map(int, line[:7])))
             if len(line) > 7:
                 e["ms"] = float(line[7])
             entries.append(e)
     return entries
+
+
+def read_staged(path: str = TUNED_FILE) -> list[dict]:
+    """The table's "staged" lines: single-shuffle classes where the staged form
+    was timed against the fused kernel, and whether bs_shuffle prefers it."""
+    out = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if not line or line[0] != "staged":
+                continue
+            e = {"elem_bytes": int(line[1]), "size_bits": int(line[2]), "prefer": int(line[3]) == 1}
+            if len(line) > 5:
+                e["ms_staged"], e["ms_fused"] = float(line[4]), float(line[5])
+            out.append(e)
+    return out
 
 
 def tune(path: str = TUNED_FILE, device: int = 0, max_size_bits: int = 0, verbose: bool = True) -> list[dict]:

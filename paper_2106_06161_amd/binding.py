@@ -61,6 +61,8 @@ _SIGNATURES = {
     "bs_unshuffle_inverse_scratch_bytes": (_sz, [_u64]),
     "bs_unshuffle_inverse": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_staged_scratch_bytes": (_sz, [_u64, _u32]),
+    "bs_workspace_bytes_staged": (_sz, [_u64, _u32]),
+    "bs_probe_set_staged_policy": (_i32, [_u32]),
     "bs_shuffle_staged": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32, _u32]),
     "bs_load_tuned_configs": (_i32, [ctypes.c_char_p]),
@@ -165,6 +167,7 @@ def bs_workspace_error(workspace, stream) -> int:
 GRID_ONE_PER_TILE = 1000
 DEPTH_COMPACT = 8  # tile schedule: kept images compacted through LDS
 DEPTH_COMPACT_PIPE = 9  # same, with the next tile's cipher overlapping the current tile's gathers
+DEPTH_STAGED = 16  # bs_query_config: bs_shuffle takes the staged form (streaming passes)
 
 
 def bs_set_config(waves: int, items: int, depth: int, grid_mult: int) -> int:
@@ -319,7 +322,12 @@ def _require_device(t, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def workspace_bytes(items: int, num_segments: int = 0, elem_bytes: int = 4) -> int:
+def workspace_bytes(items: int, num_segments: int = 0, elem_bytes: int = 4, staged: bool = False) -> int:
+    """Workspace bytes for a call; staged=True (single shuffles): room for the
+    staged form as well, which bs_shuffle then takes where the tuned table
+    prefers it."""
+    if staged and num_segments == 0:
+        return bs_workspace_bytes_staged(items, elem_bytes)
     return bs_workspace_bytes(items, num_segments, elem_bytes)
 
 
@@ -546,3 +554,11 @@ def shuffle_staged(x, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, scratch
                                scratch.numel() * scratch.element_size(), _stream_ptr(x, stream))
     _check(st, "bs_shuffle_staged")
     return out
+
+
+def bs_workspace_bytes_staged(n: int, elem_bytes: int) -> int:
+    return int(lib().bs_workspace_bytes_staged(n, elem_bytes))
+
+
+def bs_probe_set_staged_policy(mode: int) -> int:
+    return int(lib().bs_probe_set_staged_policy(mode))

@@ -67,6 +67,9 @@ bsd::LaunchConfig pick_config(uint32_t kind, uint32_t elem_bytes, uint32_t bits)
 bool g_nontemporal_store = false;
 uint32_t g_xcd_mode = 2;  // batched tile ranges per XCD: 0 off, 1 on, 2 automatic
 bool g_batch_small = true;  // batched: segments of <= 2^kSmallSegmentBits indices to one wavefront each
+// (elem_bytes, domain bits) -> bs_shuffle prefers the staged form (tuned table)
+std::map<std::pair<uint32_t, uint32_t>, bool> g_staged;
+uint32_t g_staged_policy = 2;  // 0 never, 1 whenever the workspace holds the scratch, 2 as tuned
 // look-back watchdog of later launches (spin limit, stall test hook); atomics
 // so the entry points can read them without the lock
 std::atomic<uint32_t> g_spin_limit{bsd::kSpinLimit};
@@ -226,7 +229,74 @@ bs_status check_single_args(const void* in, const void* out, uint64_t n, uint32_
   return BS_OK;
 }
 
-// One fused shuffle launch (n > 0, arguments checked); g_mu held.
+struct StagedLayout {
+  bool ok = false;
+  uint32_t k = 0, s = 0, b1 = 0, b2 = 0;
+  size_t cnt_a = 0, cnt_b = 0, base_b = 0, idx_a = 0, val_a = 0, idx_b = 0, val_b = 0, total = 0;
+};
+
+// Scratch of the staged form: counts, the window prefix, then the two bucket
+// arrays (index and record arrays each; the first pass's arrays only when
+// there are two distribution passes), every part 256-byte aligned.
+StagedLayout staged_layout(uint64_t n, uint32_t elem_bytes) {
+  StagedLayout l;
+  if (!valid_elem_bytes(elem_bytes) || n == 0 || n > BS_MAX_ITEMS) return l;
+  l.k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
+  if (!bsd::staged_digits(l.k, elem_bytes, &l.s, &l.b1, &l.b2)) return l;
+  const uint64_t domain = uint64_t(1) << l.k;
+  const uint64_t windows = uint64_t(1) << (l.b1 + l.b2);
+  l.cnt_a = 0;
+  l.cnt_b = l.cnt_a + align256((uint64_t(1) << l.b1) * 4);
+  l.base_b = l.cnt_b + align256(windows * 4);
+  l.idx_a = l.base_b + align256(windows * 4);
+  l.val_a = l.idx_a + (l.b2 ? align256(domain * 4) : 0);
+  l.idx_b = l.val_a + (l.b2 ? align256(domain * elem_bytes) : 0);
+  l.val_b = l.idx_b + align256(domain * 2);
+  l.total = l.val_b + align256(domain * elem_bytes);
+  l.ok = true;
+  return l;
+}
+
+// The staged form's launch (arguments checked, scratch of l.total bytes).
+bs_status launch_staged_form(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                             uint32_t rounds, uint8_t* scratch, const StagedLayout& l, uint32_t cus, hipStream_t s) {
+  bsd::SingleArgs c = {};
+  setup_cipher(c, n, seed, rounds);
+  bsd::StagedArgs a = {};
+  a.in = static_cast<const uint8_t*>(in);
+  a.out = static_cast<uint8_t*>(out);
+  a.n = n;
+  a.cs = c.cs;
+  a.k = l.k;
+  a.rounds = rounds;
+  a.s = l.s;
+  a.b1 = l.b1;
+  a.b2 = l.b2;
+  a.cnt_a = reinterpret_cast<uint32_t*>(scratch + l.cnt_a);
+  a.cnt_b = reinterpret_cast<uint32_t*>(scratch + l.cnt_b);
+  a.base_b = reinterpret_cast<uint32_t*>(scratch + l.base_b);
+  a.idx_a = reinterpret_cast<uint32_t*>(scratch + l.idx_a);
+  a.val_a = scratch + l.val_a;
+  a.idx_b = reinterpret_cast<uint16_t*>(scratch + l.idx_b);
+  a.val_b = scratch + l.val_b;
+  std::copy(std::begin(c.key), std::end(c.key), std::begin(a.key));
+  const hipError_t e = bsd::launch_staged(a, elem_bytes, cus, s);
+  return e == hipSuccess ? BS_OK : hip_fail(e);
+}
+
+// Whether bs_shuffle takes the staged form for (elem_bytes, k): policy 1
+// always (when the workspace holds its scratch), 2 as the tuned table says
+// (never while a shape is forced with bs_set_config); g_mu held.
+bool staged_preferred(uint32_t elem_bytes, uint32_t k) {
+  if (g_staged_policy == 1) return true;
+  if (g_staged_policy == 0 || g_forced) return false;
+  auto it = g_staged.find({elem_bytes, k});
+  return it != g_staged.end() && it->second;
+}
+
+// One bs_shuffle launch (n > 0, arguments checked); g_mu held.  The fused
+// kernel, or the staged form when preferred and the caller's workspace holds
+// its scratch after the fused part.
 bs_status launch_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t rounds,
                          void* workspace, size_t workspace_bytes, hipStream_t s) {
   const uint32_t k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
@@ -239,6 +309,20 @@ bs_status launch_shuffle(const void* in, void* out, uint64_t n, uint32_t elem_by
   const uint64_t tile = wide ? 64ull * bsd::kWideWaves * bsd::kWideItems : 64ull * cfg.waves * cfg.items;
   a.num_tiles = uint32_t((a.domain + tile - 1) / tile);
   const size_t need = align256(kHeaderBytes + single_capacity(n) * 8);
+  if (workspace && k <= 32 && staged_preferred(elem_bytes, k)) {
+    const StagedLayout l = staged_layout(n, elem_bytes);
+    if (l.ok && workspace_bytes >= need + l.total) {
+      if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return BS_EINVAL;
+      int dev = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e != hipSuccess) return hip_fail(e);
+      uint32_t cus = 0;
+      const bs_status cst = device_cus(dev, &cus);
+      if (cst != BS_OK) return cst;
+      return launch_staged_form(in, out, n, elem_bytes, seed, rounds, static_cast<uint8_t*>(workspace) + need, l,
+                                cus, s);
+    }
+  }
   void* ws = nullptr;
   bs_status st = resolve_workspace(workspace, workspace_bytes, need, s, &ws);
   if (st != BS_OK) return st;
@@ -305,6 +389,18 @@ void restore_config_state(const ConfigState& st) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_forced = st.forced;
   g_cfg = st.forced ? st.cfg : g_default_cfg;
+}
+
+void set_staged_preference(uint32_t elem_bytes, uint32_t size_bits, bool prefer) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_staged[{elem_bytes, size_bits}] = prefer;
+}
+
+std::vector<StagedEntry> staged_snapshot() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  std::vector<StagedEntry> v;
+  for (const auto& kv : g_staged) v.push_back({kv.first.first, kv.first.second, kv.second});
+  return v;
 }
 
 std::vector<TunedEntry> tuned_snapshot() {
@@ -429,6 +525,8 @@ bs_status bs_query_config(uint32_t kind, uint32_t elem_bytes, uint64_t items, ui
   const uint32_t bits = kind == 0 ? bs_domain_bits(items) : ceil_log2((items + num_segments - 1) / num_segments);
   bsd::LaunchConfig c = pick_config(kind, elem_bytes, bits);
   if (kind == 0 && bits > 32) c = {bsd::kWideWaves, bsd::kWideItems, bsd::kDepthCompactPipe, c.grid_mult};
+  if (kind == 0 && bits <= 32 && staged_preferred(elem_bytes, bits) && staged_layout(items, elem_bytes).ok)
+    c = {0, 0, BS_DEPTH_STAGED, 0};
   if (kind == 1) c = bsd::batch_config(c);
   *waves = c.waves;
   *items_per_lane = c.items;
@@ -440,6 +538,7 @@ bs_status bs_query_config(uint32_t kind, uint32_t elem_bytes, uint64_t items, ui
 bs_status bs_clear_tuned_configs(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_tuned.clear();
+  g_staged.clear();
   return BS_OK;
 }
 
@@ -812,38 +911,6 @@ extern "C" bs_status bs_unshuffle_inverse(const void* in, void* out, uint64_t n,
   return e == hipSuccess ? BS_OK : hip_fail(e);
 }
 
-namespace {
-
-struct StagedLayout {
-  bool ok = false;
-  uint32_t k = 0, s = 0, b1 = 0, b2 = 0;
-  size_t cnt_a = 0, cnt_b = 0, base_b = 0, idx_a = 0, val_a = 0, idx_b = 0, val_b = 0, total = 0;
-};
-
-// Scratch of the staged form: counts, the window prefix, then the two bucket
-// arrays (index and record arrays each; the first pass's arrays only when
-// there are two distribution passes), every part 256-byte aligned.
-StagedLayout staged_layout(uint64_t n, uint32_t elem_bytes) {
-  StagedLayout l;
-  if (!valid_elem_bytes(elem_bytes) || n == 0 || n > BS_MAX_ITEMS) return l;
-  l.k = std::max<uint32_t>(ceil_log2(n), BS_MIN_DOMAIN_BITS);
-  if (!bsd::staged_digits(l.k, elem_bytes, &l.s, &l.b1, &l.b2)) return l;
-  const uint64_t domain = uint64_t(1) << l.k;
-  const uint64_t windows = uint64_t(1) << (l.b1 + l.b2);
-  l.cnt_a = 0;
-  l.cnt_b = l.cnt_a + align256((uint64_t(1) << l.b1) * 4);
-  l.base_b = l.cnt_b + align256(windows * 4);
-  l.idx_a = l.base_b + align256(windows * 4);
-  l.val_a = l.idx_a + (l.b2 ? align256(domain * 4) : 0);
-  l.idx_b = l.val_a + (l.b2 ? align256(domain * elem_bytes) : 0);
-  l.val_b = l.idx_b + align256(domain * 4);
-  l.total = l.val_b + align256(domain * elem_bytes);
-  l.ok = true;
-  return l;
-}
-
-}  // namespace
-
 extern "C" size_t bs_staged_scratch_bytes(uint64_t n, uint32_t elem_bytes) {
   const StagedLayout l = staged_layout(n, elem_bytes);
   return l.ok ? l.total : 0;
@@ -864,27 +931,27 @@ extern "C" bs_status bs_shuffle_staged(const void* in, void* out, uint64_t n, ui
     const uint64_t bytes = n * elem_bytes;
     if ((sc < x + bytes && x < sc + l.total) || (sc < y + bytes && y < sc + l.total)) return BS_EALIAS;
   }
-  bsd::SingleArgs c = {};
-  setup_cipher(c, n, seed, rounds);
-  bsd::StagedArgs a = {};
-  a.in = static_cast<const uint8_t*>(in);
-  a.out = static_cast<uint8_t*>(out);
-  a.n = n;
-  a.cs = c.cs;
-  a.k = l.k;
-  a.rounds = rounds;
-  a.s = l.s;
-  a.b1 = l.b1;
-  a.b2 = l.b2;
-  uint8_t* base = static_cast<uint8_t*>(scratch);
-  a.cnt_a = reinterpret_cast<uint32_t*>(base + l.cnt_a);
-  a.cnt_b = reinterpret_cast<uint32_t*>(base + l.cnt_b);
-  a.base_b = reinterpret_cast<uint32_t*>(base + l.base_b);
-  a.idx_a = reinterpret_cast<uint32_t*>(base + l.idx_a);
-  a.val_a = base + l.val_a;
-  a.idx_b = reinterpret_cast<uint32_t*>(base + l.idx_b);
-  a.val_b = base + l.val_b;
-  std::copy(std::begin(c.key), std::end(c.key), std::begin(a.key));
-  const hipError_t e = bsd::launch_staged(a, elem_bytes, 0, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? BS_OK : hip_fail(e);
+  int dev = 0;
+  uint32_t cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  std::lock_guard<std::mutex> lock(g_mu);
+  const bs_status cst = device_cus(dev, &cus);
+  if (cst != BS_OK) return cst;
+  return launch_staged_form(in, out, n, elem_bytes, seed, rounds, static_cast<uint8_t*>(scratch), l, cus,
+                            static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t bs_workspace_bytes_staged(uint64_t n, uint32_t elem_bytes) {
+  if (!valid_elem_bytes(elem_bytes) || n > BS_MAX_ITEMS) return 0;
+  const size_t need = align256(kHeaderBytes + single_capacity(n) * 8);
+  const StagedLayout l = staged_layout(n, elem_bytes);
+  return l.ok ? need + l.total : need;
+}
+
+extern "C" bs_status bs_probe_set_staged_policy(uint32_t mode) {
+  if (mode > 2) return BS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_staged_policy = mode;
+  return BS_OK;
 }

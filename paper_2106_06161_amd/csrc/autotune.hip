@@ -43,6 +43,14 @@ struct Entry {
   double ms;
 };
 
+// A single-shuffle class where the staged form was timed against the fused one.
+struct StagedTiming {
+  uint32_t elem_bytes, size_bits;
+  bool prefer;
+  double ms_staged, ms_fused;
+};
+constexpr uint32_t kMinStagedBits = 20;
+
 std::vector<bsd::LaunchConfig> candidates() {
   std::vector<bsd::LaunchConfig> shapes;
 #define BSD_ADD(W, I, D) shapes.push_back({W, I, D, 0});
@@ -82,7 +90,8 @@ uint64_t splitmix64(uint64_t& state) {
   return z ^ (z >> 31);
 }
 
-bool parse_table(const char* path, std::string* arch, std::vector<Entry>* out) {
+bool parse_table(const char* path, std::string* arch, std::vector<Entry>* out,
+                 std::vector<StagedTiming>* staged) {
   std::ifstream f(path);
   if (!f) return false;
   std::string line;
@@ -97,6 +106,15 @@ bool parse_table(const char* path, std::string* arch, std::vector<Entry>* out) {
       continue;
     }
     if (first == "rounds") continue;
+    if (first == "staged") {
+      StagedTiming t = {};
+      uint32_t prefer = 0;
+      if (!(ls >> t.elem_bytes >> t.size_bits >> prefer) || prefer > 1) return false;
+      t.prefer = prefer != 0;
+      ls >> t.ms_staged >> t.ms_fused;
+      staged->push_back(t);
+      continue;
+    }
     Entry e = {};
     std::istringstream all(line);
     if (!(all >> e.kind >> e.elem_bytes >> e.size_bits >> e.cfg.waves >> e.cfg.items >> e.cfg.depth >>
@@ -109,7 +127,8 @@ bool parse_table(const char* path, std::string* arch, std::vector<Entry>* out) {
   return true;
 }
 
-bool write_table(const char* path, const std::string& arch, const std::vector<Entry>& entries) {
+bool write_table(const char* path, const std::string& arch, const std::vector<Entry>& entries,
+                 const std::vector<StagedTiming>& staged) {
   FILE* f = std::fopen(path, "w");
   if (!f) return false;
   std::fprintf(f, "# libbshuffle tuned launch shapes (bs_autotune)\n");
@@ -118,18 +137,27 @@ bool write_table(const char* path, const std::string& arch, const std::vector<En
   for (const auto& e : entries)
     std::fprintf(f, "%u %u %u %u %u %u %u %.4f\n", e.kind, e.elem_bytes, e.size_bits, e.cfg.waves, e.cfg.items,
                  e.cfg.depth, e.cfg.grid_mult, e.ms);
+  if (!staged.empty()) std::fprintf(f, "# staged elem_bytes size_bits prefer ms_staged ms_fused\n");
+  for (const auto& t : staged)
+    std::fprintf(f, "staged %u %u %u %.4f %.4f\n", t.elem_bytes, t.size_bits, t.prefer ? 1u : 0u, t.ms_staged,
+                 t.ms_fused);
   return std::fclose(f) == 0;
 }
 
-bs_status install(const std::vector<Entry>& entries) {
+bs_status install(const std::vector<Entry>& entries, const std::vector<StagedTiming>& staged) {
   for (const auto& e : entries)
     if (e.kind > 1 || e.size_bits > 40 || !bsd::config_supported(e.cfg)) return BS_EINVAL;
+  for (const auto& t : staged)
+    if (t.size_bits > 40 || !(t.elem_bytes == 1 || t.elem_bytes == 2 || t.elem_bytes == 4 || t.elem_bytes == 8 ||
+                              t.elem_bytes == 16))
+      return BS_EINVAL;
   bs_clear_tuned_configs();
   for (const auto& e : entries) {
     const bs_status st = bs_set_tuned_config(e.kind, e.elem_bytes, e.size_bits, e.cfg.waves, e.cfg.items,
                                              e.cfg.depth, e.cfg.grid_mult);
     if (st != BS_OK) return st;
   }
+  for (const auto& t : staged) bsd::set_staged_preference(t.elem_bytes, t.size_bits, t.prefer);
   return BS_OK;
 }
 
@@ -178,6 +206,35 @@ bs_status tune_single(uint32_t eb, uint32_t bits, hipStream_t s, hipEvent_t e0, 
     if (best->ms < 0 || t_hi + t_lo < best->ms) *best = {0, eb, bits, c, t_hi + t_lo};
   }
   return best->ms < 0 ? BS_EHIP : BS_OK;
+}
+
+// The staged form on the same two sizes as tune_single, against the best
+// fused time; false (nothing timed) when it does not cover the class or its
+// scratch does not fit `budget`.
+bool tune_staged(uint32_t eb, uint32_t bits, double fused_ms, uint64_t budget, hipStream_t s, hipEvent_t e0,
+                 hipEvent_t e1, StagedTiming* out) {
+  const uint64_t hi = uint64_t(1) << bits, lo = (hi >> 1) + 1;
+  const size_t scratch_bytes = bs_staged_scratch_bytes(hi, eb);
+  if (bits < kMinStagedBits || scratch_bytes == 0 || bs_staged_scratch_bytes(lo, eb) == 0 ||
+      scratch_bytes + 2 * hi * eb > budget)
+    return false;
+  DeviceBuffers b;
+  void* scratch = nullptr;
+  if (hipMalloc(&b.in, hi * eb) != hipSuccess || hipMalloc(&b.out, hi * eb) != hipSuccess ||
+      hipMalloc(&scratch, scratch_bytes) != hipSuccess)
+    return false;
+  bool ok = hipMemsetAsync(b.in, 0x5A, hi * eb, s) == hipSuccess;
+  double t_hi = 0, t_lo = 0;
+  ok = ok &&
+       time_best([&] { return bs_shuffle_staged(b.in, b.out, hi, eb, 7, kTuneRounds, scratch, scratch_bytes, s); },
+                 s, e0, e1, &t_hi) == BS_OK &&
+       time_best([&] { return bs_shuffle_staged(b.in, b.out, lo, eb, 7, kTuneRounds, scratch, scratch_bytes, s); },
+                 s, e0, e1, &t_lo) == BS_OK;
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  if (!ok) return false;
+  *out = {eb, bits, t_hi + t_lo < fused_ms, t_hi + t_lo, fused_ms};
+  return true;
 }
 
 bs_status tune_batched(uint32_t eb, uint32_t bits, uint64_t batch_items, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
@@ -230,13 +287,19 @@ bs_status tune_batched(uint32_t eb, uint32_t bits, uint64_t batch_items, hipStre
   return result;
 }
 
+void report_staged(const StagedTiming& t, bool verbose) {
+  if (verbose)
+    std::fprintf(stderr, "bs_autotune: staged elem_bytes %u size_bits %u: %.4f ms against %.4f ms fused -> %s\n",
+                 t.elem_bytes, t.size_bits, t.ms_staged, t.ms_fused, t.prefer ? "staged" : "fused");
+}
+
 void report(const Entry& e, bool verbose) {
   if (verbose)
     std::fprintf(stderr, "bs_autotune: kind %u elem_bytes %u size_bits %u -> %u %u %u %u (%.4f ms)\n", e.kind,
                  e.elem_bytes, e.size_bits, e.cfg.waves, e.cfg.items, e.cfg.depth, e.cfg.grid_mult, e.ms);
 }
 
-bs_status tune_device(uint32_t max_bits, bool verbose, std::vector<Entry>* out) {
+bs_status tune_device(uint32_t max_bits, bool verbose, std::vector<Entry>* out, std::vector<StagedTiming>* staged) {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return BS_EHIP;
   const uint64_t budget = std::min<uint64_t>(free_b / 2, kMaxTuneBytes);
@@ -257,6 +320,11 @@ bs_status tune_device(uint32_t max_bits, bool verbose, std::vector<Entry>* out) 
       if (st == BS_OK) {
         report(e, verbose);
         out->push_back(e);
+        StagedTiming t;
+        if (tune_staged(eb, bits, e.ms, budget, s, e0, e1, &t)) {
+          report_staged(t, verbose);
+          staged->push_back(t);
+        }
       }
     }
     for (uint32_t bits = kMinBatchBits; st == BS_OK && bits <= std::min(max_bits, kMaxBatchBits); ++bits) {
@@ -285,8 +353,9 @@ extern "C" bs_status bs_load_tuned_configs(const char* path) {
   if (!path) return BS_EINVAL;
   std::string arch;
   std::vector<Entry> entries;
-  if (!parse_table(path, &arch, &entries)) return BS_EINVAL;
-  return install(entries);
+  std::vector<StagedTiming> staged;
+  if (!parse_table(path, &arch, &entries, &staged)) return BS_EINVAL;
+  return install(entries, staged);
 }
 
 extern "C" bs_status bs_save_tuned_configs(const char* path) {
@@ -296,7 +365,9 @@ extern "C" bs_status bs_save_tuned_configs(const char* path) {
   if (hipGetDevice(&dev) == hipSuccess) arch = device_arch(dev);
   std::vector<Entry> entries;
   for (const auto& t : bsd::tuned_snapshot()) entries.push_back({t.kind, t.elem_bytes, t.size_bits, t.cfg, 0.0});
-  return write_table(path, arch, entries) ? BS_OK : BS_EINVAL;
+  std::vector<StagedTiming> staged;
+  for (const auto& t : bsd::staged_snapshot()) staged.push_back({t.elem_bytes, t.size_bits, t.prefer, 0.0, 0.0});
+  return write_table(path, arch, entries, staged) ? BS_OK : BS_EINVAL;
 }
 
 extern "C" bs_status bs_autotune(int device, const char* cache_path, uint32_t max_size_bits, uint32_t flags) {
@@ -308,18 +379,21 @@ extern "C" bs_status bs_autotune(int device, const char* cache_path, uint32_t ma
   if (cache_path) {
     std::string file_arch;
     std::vector<Entry> cached;
-    if (parse_table(cache_path, &file_arch, &cached) && file_arch == arch && !cached.empty())
-      return install(cached);
+    std::vector<StagedTiming> cached_staged;
+    if (parse_table(cache_path, &file_arch, &cached, &cached_staged) && file_arch == arch && !cached.empty())
+      return install(cached, cached_staged);
   }
   int prev = 0;
   if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return BS_EHIP;
   const bsd::ConfigState saved = bsd::config_state();
   std::vector<Entry> entries;
-  bs_status st = tune_device(max_size_bits ? max_size_bits : kMaxSingleBits, flags & BS_AUTOTUNE_VERBOSE, &entries);
+  std::vector<StagedTiming> staged;
+  bs_status st = tune_device(max_size_bits ? max_size_bits : kMaxSingleBits, flags & BS_AUTOTUNE_VERBOSE, &entries,
+                             &staged);
   bsd::restore_config_state(saved);
   (void)hipSetDevice(prev);
   if (st != BS_OK) return st;
-  st = install(entries);
-  if (st == BS_OK && cache_path && !write_table(cache_path, arch, entries)) st = BS_EINVAL;
+  st = install(entries, staged);
+  if (st == BS_OK && cache_path && !write_table(cache_path, arch, entries, staged)) st = BS_EINVAL;
   return st;
 }

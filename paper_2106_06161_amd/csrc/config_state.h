@@ -26,4 +26,12 @@ struct TunedEntry {
 };
 std::vector<TunedEntry> tuned_snapshot();
 
+// Single-shuffle size classes where bs_shuffle prefers the staged form.
+struct StagedEntry {
+  uint32_t elem_bytes, size_bits;
+  bool prefer;
+};
+void set_staged_preference(uint32_t elem_bytes, uint32_t size_bits, bool prefer);
+std::vector<StagedEntry> staged_snapshot();
+
 }  // namespace bsd

@@ -121,7 +121,7 @@ struct StagedArgs {
   uint32_t* idx_a;
   uint8_t* val_a;
   uint32_t* cnt_a;   // 2^b1 bucket counts
-  uint32_t* idx_b;
+  uint16_t* idx_b;   // low 16 bits of the padded index (the place pass needs i mod 2^s, s <= 16)
   uint8_t* val_b;
   uint32_t* cnt_b;   // 2^(b1 + b2) window counts
   uint32_t* base_b;  // exclusive prefix of cnt_b

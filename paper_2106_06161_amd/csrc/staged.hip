@@ -27,13 +27,26 @@
 namespace bsd {
 namespace {
 
-constexpr uint32_t kDistThreads = 256;
-constexpr uint32_t kDistItems = 16;
-constexpr uint32_t kDistTile = kDistThreads * kDistItems;  // records per distribution tile
 constexpr uint32_t kMaxDigitBits = 9;
 constexpr uint32_t kMaxDigits = 1u << kMaxDigitBits;
 constexpr uint32_t kPlaceThreads = 1024;
 constexpr uint32_t kScanThreads = 1024;
+
+// Tile shapes of the two distribution passes.  The first pass takes as many
+// records per tile as its LDS staging area holds with one workgroup per CU:
+// every record of a tile that lands in the same bucket shares one global
+// reservation, and all tiles reserve from the same 2^b1 counters, so large
+// tiles keep those few counters from serializing the pass.  The second pass
+// spreads its reservations over 2^(b1 + b2) window counters and uses 4,096-
+// record tiles with several workgroups per CU.
+template <int EB, int PASS>
+struct DistShape {
+  static constexpr uint32_t kThreads = PASS == 1 ? 1024u : (EB <= 4 ? 256u : EB == 8 ? 512u : 1024u);
+  static constexpr uint32_t kTile = PASS == 1 ? (EB <= 4 ? 16384u : EB == 8 ? 8192u : 4096u) : 4096u;
+  static constexpr uint32_t kItems = kTile / kThreads;
+  static constexpr uint32_t kDigitsPerThread = (kMaxDigits + kThreads - 1) / kThreads;
+};
+constexpr uint32_t kMaxFirstTile = 16384;
 
 // Exclusive scan over a workgroup of THREADS threads; *total gets the sum.
 // Uses waves[THREADS / 64] words of LDS; ends with a barrier.
@@ -60,45 +73,68 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
   return before + incl - v;
 }
 
-template <int EB>
+template <int EB, typename S>
 struct DistLds {
   uint32_t hist[kMaxDigits];
   uint32_t start[kMaxDigits];
   uint32_t gbase[kMaxDigits];
-  uint32_t waves[kDistThreads / 64];
-  uint32_t idx[kDistTile];
-  typename Payload<EB>::T val[kDistTile];
+  uint32_t waves[S::kThreads / 64];
+  uint32_t idx[S::kTile];
+  typename Payload<EB>::T val[S::kTile];
 };
 
-// Sorts one tile of (i, record) entries by digit (i >> shift) & (digits - 1)
-// through LDS and appends each digit's run to bucket `bucket_first + digit`
-// (capacity `cap` entries each).  pos[j] holds entry j's position within its
-// digit (from the LDS histogram) on entry; entries with valid bit j clear
-// are skipped.  Called by the whole workgroup.
-template <int EB>
-__device__ __forceinline__ void append_runs(DistLds<EB>& lds, const uint32_t (&i)[kDistItems],
-                                            const typename Payload<EB>::T (&v)[kDistItems],
-                                            const uint32_t (&pos)[kDistItems], uint32_t valid, uint32_t shift,
-                                            uint32_t digits, uint64_t bucket_first, uint64_t cap,
-                                            uint32_t* __restrict__ idx_out, uint8_t* __restrict__ val_out,
-                                            uint32_t* __restrict__ counts) {
+// One distribution tile of (i, record) entries, sorted by digit
+// (i >> shift) & (digits - 1) through LDS and appended to bucket
+// `bucket_first + digit` (capacity `cap` entries each), in four steps so a
+// caller can overlap the global reservations' latency with other work:
+//   reserve_runs    scan of the LDS histogram -> digit starts in the tile;
+//                   one global atomic per digit reserves its run (results
+//                   stay in registers)
+//   stage_entries   entries to LDS at start[digit] + their position
+//   publish_bases   the reserved run bases to LDS (waits for the atomics)
+//   write_runs      each run to its bucket; consecutive threads write
+//                   consecutive entries of a run.  Windows (the second
+//                   level, or the first with one pass) keep only the low 16
+//                   bits of i: the place pass needs i mod 2^s, s <= 16.
+template <typename S>
+struct Reservation {
+  uint32_t h[S::kDigitsPerThread];  // this thread's digits: entries in the tile
+  uint32_t g[S::kDigitsPerThread];  // and the reserved position in their bucket
+  uint32_t count;                   // entries in the tile
+};
+
+template <int EB, typename S>
+__device__ __forceinline__ void reserve_runs(DistLds<EB, S>& lds, Reservation<S>& r, uint32_t digits,
+                                             uint64_t bucket_first, uint32_t* __restrict__ counts) {
+  constexpr uint32_t kPer = S::kDigitsPerThread;
   const uint32_t tid = threadIdx.x;
-  // digit starts within the tile (two digits per thread: digits <= 512)
-  const uint32_t d0 = 2 * tid, d1 = 2 * tid + 1;
-  const uint32_t h0 = d0 < digits ? lds.hist[d0] : 0u, h1 = d1 < digits ? lds.hist[d1] : 0u;
-  uint32_t count;
-  const uint32_t s0 = block_exclusive_scan<kDistThreads>(h0 + h1, lds.waves, &count);
-  if (d0 < digits) {
-    lds.start[d0] = s0;
-    if (h0) lds.gbase[d0] = atomicAdd(&counts[bucket_first + d0], h0);
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t d = tid * kPer + j;
+    r.h[j] = d < digits ? lds.hist[d] : 0u;
+    sum += r.h[j];
   }
-  if (d1 < digits) {
-    lds.start[d1] = s0 + h0;
-    if (h1) lds.gbase[d1] = atomicAdd(&counts[bucket_first + d1], h1);
+  uint32_t run = block_exclusive_scan<S::kThreads>(sum, lds.waves, &r.count);
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t d = tid * kPer + j;
+    if (d < digits) {
+      lds.start[d] = run;
+      r.g[j] = r.h[j] ? atomicAdd(&counts[bucket_first + d], r.h[j]) : 0u;
+    }
+    run += r.h[j];
   }
   __syncthreads();
+}
+
+template <int EB, typename S>
+__device__ __forceinline__ void stage_entries(DistLds<EB, S>& lds, const uint32_t (&i)[S::kItems],
+                                              const typename Payload<EB>::T (&v)[S::kItems],
+                                              const uint32_t (&pos)[S::kItems], uint32_t valid, uint32_t shift,
+                                              uint32_t digits) {
 #pragma unroll
-  for (uint32_t j = 0; j < kDistItems; ++j) {
+  for (uint32_t j = 0; j < S::kItems; ++j) {
     if ((valid >> j) & 1u) {
       const uint32_t d = (i[j] >> shift) & (digits - 1);
       const uint32_t p = lds.start[d] + pos[j];
@@ -106,96 +142,150 @@ __device__ __forceinline__ void append_runs(DistLds<EB>& lds, const uint32_t (&i
       lds.val[p] = v[j];
     }
   }
+}
+
+template <int EB, typename S>
+__device__ __forceinline__ void publish_bases(DistLds<EB, S>& lds, const Reservation<S>& r, uint32_t digits) {
+  constexpr uint32_t kPer = S::kDigitsPerThread;
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t d = threadIdx.x * kPer + j;
+    if (d < digits && r.h[j]) lds.gbase[d] = r.g[j];
+  }
   __syncthreads();
-  for (uint32_t p = tid; p < count; p += kDistThreads) {
+}
+
+template <int EB, typename S>
+__device__ __forceinline__ void write_runs(DistLds<EB, S>& lds, uint32_t count, uint32_t shift, uint32_t digits,
+                                           uint64_t bucket_first, uint64_t cap, void* __restrict__ idx_out,
+                                           bool windows, uint8_t* __restrict__ val_out) {
+  for (uint32_t p = threadIdx.x; p < count; p += S::kThreads) {
     const uint32_t ii = lds.idx[p];
     const uint32_t d = (ii >> shift) & (digits - 1);
     const uint64_t g = (bucket_first + d) * cap + lds.gbase[d] + (p - lds.start[d]);
-    idx_out[g] = ii;
+    if (windows)
+      static_cast<uint16_t*>(idx_out)[g] = uint16_t(ii);
+    else
+      static_cast<uint32_t*>(idx_out)[g] = ii;
     store_record<EB, false>(val_out, g, lds.val[p]);
   }
   __syncthreads();
 }
 
 // First distribution pass: records in input order, i = f^-1(y), digit =
-// i >> (k - b1).  With b2 == 0 the digit is already the window.
+// i >> (k - b1).  With b2 == 0 the digit is already the window.  Persistent:
+// a workgroup walks tiles gridDim.x apart; the next tile's loads and cipher
+// (the pass's VALU work) run while the current tile's reservations are in
+// flight, and the loads stay in flight through the current tile's writes.
+template <int EB, typename S>
+__device__ __forceinline__ uint32_t load_tile(typename Payload<EB>::T (&v)[S::kItems], uint32_t (&L)[S::kItems],
+                                              uint32_t (&R)[S::kItems], const StagedArgs& a, uint64_t tile) {
+  const uint64_t y0 = tile * S::kTile;
+  uint32_t valid = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < S::kItems; ++j) {
+    const uint64_t y = y0 + j * S::kThreads + threadIdx.x;
+    const bool ok = y < a.n;
+    const uint64_t yc = ok ? y : a.n - 1;  // idle lanes re-read the last record and keep nothing
+    valid |= ok ? (1u << j) : 0u;
+    v[j] = load_record<EB>(a.in, yc);
+    L[j] = uint32_t(yc >> a.cs.r) & a.cs.wmask;
+    R[j] = uint32_t(yc) & a.cs.rmask;
+  }
+  return valid;
+}
+
 template <int EB, bool ODD>
-__global__ __launch_bounds__(kDistThreads) void staged_first_kernel(const StagedArgs a) {
+__global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_first_kernel(const StagedArgs a) {
+  using S = DistShape<EB, 1>;
   using T = typename Payload<EB>::T;
-  __shared__ DistLds<EB> lds;
+  constexpr uint32_t kItems = S::kItems;
+  __shared__ DistLds<EB, S> lds;
   const uint32_t tid = threadIdx.x;
   const uint32_t digits = 1u << a.b1;
   const uint32_t shift = a.k - a.b1;
   const uint64_t cap = uint64_t(1) << shift;
-  uint32_t* idx_out = a.b2 ? a.idx_a : a.idx_b;
-  uint8_t* val_out = a.b2 ? a.val_a : a.val_b;
-  uint32_t* counts = a.b2 ? a.cnt_a : a.cnt_b;
-  const uint64_t tiles = (a.n + kDistTile - 1) / kDistTile;
-  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    for (uint32_t d = tid; d < digits; d += kDistThreads) lds.hist[d] = 0;
+  const bool windows = a.b2 == 0;
+  void* idx_out = windows ? static_cast<void*>(a.idx_b) : static_cast<void*>(a.idx_a);
+  uint8_t* val_out = windows ? a.val_b : a.val_a;
+  uint32_t* counts = windows ? a.cnt_b : a.cnt_a;
+  const uint64_t tiles = (a.n + S::kTile - 1) / S::kTile;
+  uint64_t tile = blockIdx.x;
+  if (tile >= tiles) return;
+  T v[kItems];
+  uint32_t L[kItems], R[kItems], pos[kItems];
+  uint32_t valid = load_tile<EB, S>(v, L, R, a, tile);
+  vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+  for (;;) {
+    for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
     __syncthreads();
-    const uint64_t y0 = tile * kDistTile;
-    T v[kDistItems];
-    uint32_t L[kDistItems], R[kDistItems], pos[kDistItems];
-    uint32_t valid = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < kDistItems; ++j) {
-      const uint64_t y = y0 + j * kDistThreads + tid;
-      const bool ok = y < a.n;
-      const uint64_t yc = ok ? y : a.n - 1;  // idle lanes re-read the last record and keep nothing
-      valid |= ok ? (1u << j) : 0u;
-      v[j] = load_record<EB>(a.in, yc);
-      L[j] = uint32_t(yc >> a.cs.r) & a.cs.wmask;
-      R[j] = uint32_t(yc) & a.cs.rmask;
-    }
-    vp_decrypt<ODD, kDistItems>(L, R, a.cs, a.rounds, a.key);
-#pragma unroll
-    for (uint32_t j = 0; j < kDistItems; ++j) {
+    for (uint32_t j = 0; j < kItems; ++j) {
       L[j] = (L[j] << a.cs.r) | R[j];  // the padded index i whose image is y
       pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[L[j] >> shift], 1u) : 0u;
     }
     __syncthreads();
-    append_runs<EB>(lds, L, v, pos, valid, shift, digits, 0, cap, idx_out, val_out, counts);
+    Reservation<S> res;
+    reserve_runs<EB, S>(lds, res, digits, 0, counts);
+    stage_entries<EB, S>(lds, L, v, pos, valid, shift, digits);
+    const uint64_t next = tile + gridDim.x;
+    const bool more = next < tiles;
+    if (more) {
+      valid = load_tile<EB, S>(v, L, R, a, next);
+      vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+    }
+    publish_bases<EB, S>(lds, res, digits);
+    write_runs<EB, S>(lds, res.count, shift, digits, 0, cap, idx_out, windows, val_out);
+    if (!more) break;
+    tile = next;
   }
 }
 
 // Second distribution pass: bucket d1's entries, digit = (i >> s) & (2^b2 -
 // 1), appended to window d1 * 2^b2 + digit.  Work item w covers entries
-// [c * tile, (c + 1) * tile) of bucket w / chunks.
+// [c * tile, (c + 1) * tile) of bucket w / chunks; items past a bucket's
+// count exit at once (about half of them: a bucket holds the kept share of
+// its capacity).
 template <int EB>
-__global__ __launch_bounds__(kDistThreads) void staged_second_kernel(const StagedArgs a) {
+__global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_kernel(const StagedArgs a) {
+  using S = DistShape<EB, 2>;
   using T = typename Payload<EB>::T;
-  __shared__ DistLds<EB> lds;
+  constexpr uint32_t kItems = S::kItems;
+  __shared__ DistLds<EB, S> lds;
   const uint32_t tid = threadIdx.x;
   const uint32_t digits = 1u << a.b2;
   const uint64_t cap_a = uint64_t(1) << (a.k - a.b1);
   const uint64_t cap_b = uint64_t(1) << a.s;
-  const uint64_t chunks = cap_a / kDistTile;
+  const uint64_t chunks = cap_a / S::kTile;
   const uint64_t work = (uint64_t(1) << a.b1) * chunks;
   for (uint64_t w = blockIdx.x; w < work; w += gridDim.x) {
     const uint64_t d1 = w / chunks;
-    const uint64_t first = (w % chunks) * kDistTile;
+    const uint64_t first = (w % chunks) * S::kTile;
     const uint32_t cnt = a.cnt_a[d1];
     if (first >= cnt) continue;  // uniform across the workgroup
-    for (uint32_t d = tid; d < digits; d += kDistThreads) lds.hist[d] = 0;
-    __syncthreads();
-    T v[kDistItems];
-    uint32_t ii[kDistItems], pos[kDistItems];
+    for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
+    T v[kItems];
+    uint32_t ii[kItems], pos[kItems];
     uint32_t valid = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < kDistItems; ++j) {
-      const uint64_t e = first + j * kDistThreads + tid;
+    for (uint32_t j = 0; j < kItems; ++j) {
+      const uint64_t e = first + j * S::kThreads + tid;
       const bool ok = e < cnt;
-      const uint64_t g = d1 * cap_a + (ok ? e : first);
       valid |= ok ? (1u << j) : 0u;
+      const uint64_t g = d1 * cap_a + (ok ? e : first);
       ii[j] = a.idx_a[g];
       v[j] = load_record<EB>(a.val_a, g);
     }
+    __syncthreads();  // the histogram is cleared
 #pragma unroll
-    for (uint32_t j = 0; j < kDistItems; ++j)
+    for (uint32_t j = 0; j < kItems; ++j)
       pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[(ii[j] >> a.s) & (digits - 1)], 1u) : 0u;
     __syncthreads();
-    append_runs<EB>(lds, ii, v, pos, valid, a.s, digits, d1 << a.b2, cap_b, a.idx_b, a.val_b, a.cnt_b);
+    Reservation<S> res;
+    reserve_runs<EB, S>(lds, res, digits, d1 << a.b2, a.cnt_b);
+    stage_entries<EB, S>(lds, ii, v, pos, valid, a.s, digits);
+    publish_bases<EB, S>(lds, res, digits);
+    write_runs<EB, S>(lds, res.count, a.s, digits, d1 << a.b2, cap_b, a.idx_b, true, a.val_b);
   }
 }
 
@@ -228,14 +318,33 @@ __global__ __launch_bounds__(kScanThreads) void staged_scan_kernel(const StagedA
 template <int EB>
 constexpr uint32_t kWindowBits = EB == 1 ? 16 : EB == 2 ? 15 : EB == 4 ? 14 : EB == 8 ? 13 : 12;
 
-// One workgroup per window q of 2^s padded indices: its records go to LDS at
-// i mod 2^s with a kept bit; each thread owns 2^S / kPlaceThreads consecutive
-// slots, counts its kept bits, takes its start from a workgroup scan, and
-// moves its records to their ranks; the window is then written in order at
-// out[base_b[q]].  (s < S only when the whole domain is one window.)
+// One workgroup per window q of 2^s padded indices at a time (persistent:
+// windows gridDim.x apart): its records go to LDS at i mod 2^s with a kept
+// bit; each thread owns 2^S / kPlaceThreads consecutive slots, counts its
+// kept bits, takes its start from a workgroup scan, and moves its records to
+// their ranks; the window is then written in order at out[base_b[q]].  The
+// first kPrefetch entries per thread of the next window are loaded while the
+// current one is ranked and written.  (s < S only when the whole domain is
+// one window.)
+constexpr uint32_t kPrefetch = 4;
+
+template <typename T>
+__device__ __forceinline__ void load_window_head(uint32_t (&il)[kPrefetch], T (&v)[kPrefetch],
+                                                 const StagedArgs& a, uint32_t q, uint32_t cnt, uint32_t wmask) {
+  const uint64_t first = uint64_t(q) << a.s;
+#pragma unroll
+  for (uint32_t j = 0; j < kPrefetch; ++j) {
+    const uint32_t e = threadIdx.x + j * kPlaceThreads;
+    const uint64_t g = first + (e < cnt ? e : 0u);
+    il[j] = a.idx_b[g] & wmask;
+    v[j] = reinterpret_cast<const T*>(a.val_b)[g];
+  }
+}
+
 template <int EB>
-__global__ __launch_bounds__(kPlaceThreads) void staged_place_kernel(const StagedArgs a) {
-  using T = typename Payload<EB>::T;
+__global__ __launch_bounds__(kPlaceThreads, 8) void staged_place_kernel(const StagedArgs a) {
+  // records move as plain words here (16-byte records as one 4-word vector)
+  using T = std::conditional_t<EB == 16, u32x4, typename Payload<EB>::T>;
   constexpr uint32_t S = kWindowBits<EB>;
   constexpr uint32_t W = 1u << S;
   constexpr uint32_t kPer = W / kPlaceThreads;  // slots per thread: 4 .. 64
@@ -245,16 +354,35 @@ __global__ __launch_bounds__(kPlaceThreads) void staged_place_kernel(const Stage
   __shared__ uint32_t waves[kPlaceThreads / 64];
   const uint32_t tid = threadIdx.x;
   const uint32_t windows = 1u << (a.b1 + a.b2);
-  for (uint32_t q = blockIdx.x; q < windows; q += gridDim.x) {
-    const uint32_t cnt = a.cnt_b[q];
+  uint32_t q = blockIdx.x;
+  if (q >= windows) return;
+  uint32_t il[kPrefetch];
+  T hv[kPrefetch];
+  uint32_t cnt = a.cnt_b[q];
+  load_window_head<T>(il, hv, a, q, cnt, W - 1);
+  for (;;) {
     const uint64_t base = a.base_b[q];
     for (uint32_t t = tid; t < W / 32; t += kPlaceThreads) bits[t] = 0;
     __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kPrefetch; ++j) {
+      if (tid + j * kPlaceThreads < cnt) {
+        vals[il[j]] = hv[j];
+        atomicOr(&bits[il[j] >> 5], 1u << (il[j] & 31));
+      }
+    }
     const uint64_t first = uint64_t(q) << a.s;
-    for (uint32_t e = tid; e < cnt; e += kPlaceThreads) {
-      const uint32_t il = a.idx_b[first + e] & (W - 1);
-      vals[il] = load_record<EB>(a.val_b, first + e);
-      atomicOr(&bits[il >> 5], 1u << (il & 31));
+    for (uint32_t e = tid + kPrefetch * kPlaceThreads; e < cnt; e += kPlaceThreads) {
+      const uint32_t x = a.idx_b[first + e] & (W - 1);
+      vals[x] = reinterpret_cast<const T*>(a.val_b)[first + e];
+      atomicOr(&bits[x >> 5], 1u << (x & 31));
+    }
+    const uint32_t cur_cnt = cnt;
+    const uint32_t next = q + gridDim.x;
+    const bool more = next < windows;
+    if (more) {
+      cnt = a.cnt_b[next];
+      load_window_head<T>(il, hv, a, next, cnt, W - 1);
     }
     __syncthreads();
     const uint32_t slot0 = tid * kPer;
@@ -271,33 +399,50 @@ __global__ __launch_bounds__(kPlaceThreads) void staged_place_kernel(const Stage
     for (uint32_t j = 0; j < kPer; ++j) r[j] = vals[slot0 + j];
     uint32_t total;
     const uint32_t start = block_exclusive_scan<kPlaceThreads>(uint32_t(__builtin_popcountll(mine)), waves, &total);
-    uint32_t p = start;
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-      if ((mine >> j) & 1u) vals[p++] = r[j];
+      const uint64_t below = mine & ((uint64_t(1) << j) - 1u);
+      if ((mine >> j) & 1u) vals[start + uint32_t(__builtin_popcountll(below))] = r[j];
     }
     __syncthreads();
-    for (uint32_t t = tid; t < cnt; t += kPlaceThreads) store_record<EB, false>(a.out, base + t, vals[t]);
+    for (uint32_t t = tid; t < cur_cnt; t += kPlaceThreads) reinterpret_cast<T*>(a.out)[base + t] = vals[t];
     __syncthreads();
+    if (!more) break;
+    q = next;
   }
+}
+
+// Workgroups of fn that stay resident on the device at once.
+uint32_t resident_groups(const void* fn, uint32_t threads, uint32_t num_cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, int(threads), 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return uint32_t(per_cu) * (num_cus ? num_cus : 1);
 }
 
 template <int EB>
 hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hipStream_t stream) {
+  using S1 = DistShape<EB, 1>;
+  using S2 = DistShape<EB, 2>;
   const uint32_t zero_groups = std::max(1u, std::min(256u, (1u << (a.b1 + a.b2)) / 256u));
   hipLaunchKernelGGL(staged_zero_kernel, dim3(zero_groups), dim3(256), 0, stream, a);
-  const uint64_t tiles = (a.n + kDistTile - 1) / kDistTile;
-  const dim3 g1(uint32_t(tiles < (1u << 20) ? tiles : (1u << 20)));
+  // first pass: persistent, as many workgroups as stay resident
+  const uint64_t tiles = (a.n + S1::kTile - 1) / S1::kTile;
+  const void* first = odd ? reinterpret_cast<const void*>(&staged_first_kernel<EB, true>)
+                          : reinterpret_cast<const void*>(&staged_first_kernel<EB, false>);
+  const uint64_t r1 = resident_groups(first, S1::kThreads, num_cus);
+  const dim3 g1(uint32_t(tiles < r1 ? tiles : r1));
   if (odd)
-    hipLaunchKernelGGL((staged_first_kernel<EB, true>), g1, dim3(kDistThreads), 0, stream, a);
+    hipLaunchKernelGGL((staged_first_kernel<EB, true>), g1, dim3(S1::kThreads), 0, stream, a);
   else
-    hipLaunchKernelGGL((staged_first_kernel<EB, false>), g1, dim3(kDistThreads), 0, stream, a);
+    hipLaunchKernelGGL((staged_first_kernel<EB, false>), g1, dim3(S1::kThreads), 0, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.b2) {
-    const uint64_t work = (uint64_t(1) << a.b1) * ((uint64_t(1) << (a.k - a.b1)) / kDistTile);
-    const dim3 g2(uint32_t(work < (1u << 20) ? work : (1u << 20)));
-    hipLaunchKernelGGL((staged_second_kernel<EB>), g2, dim3(kDistThreads), 0, stream, a);
+    // second pass: one workgroup per work item (most of the empty ones exit at once)
+    const uint64_t work = (uint64_t(1) << a.b1) * ((uint64_t(1) << (a.k - a.b1)) / S2::kTile);
+    const dim3 g2(uint32_t(work < (1u << 24) ? work : (1u << 24)));
+    hipLaunchKernelGGL((staged_second_kernel<EB>), g2, dim3(S2::kThreads), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -305,8 +450,10 @@ hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hip
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t windows = 1u << (a.b1 + a.b2);
-  hipLaunchKernelGGL((staged_place_kernel<EB>), dim3(windows), dim3(kPlaceThreads), 0, stream, a);
-  (void)num_cus;
+  const uint32_t r3 = resident_groups(reinterpret_cast<const void*>(&staged_place_kernel<EB>), kPlaceThreads,
+                                      num_cus);
+  hipLaunchKernelGGL((staged_place_kernel<EB>), dim3(windows < r3 ? windows : r3), dim3(kPlaceThreads), 0, stream,
+                     a);
   return hipGetLastError();
 }
 
@@ -341,7 +488,7 @@ bool staged_digits(uint32_t k, uint32_t elem_bytes, uint32_t* s, uint32_t* b1, u
     *b2 = nb - *b1;
   }
   // the second pass reads first-pass buckets in whole distribution tiles
-  if (*b2 && (uint64_t(1) << (k - *b1)) < kDistTile) return false;
+  if (*b2 && (uint64_t(1) << (k - *b1)) < kMaxFirstTile) return false;
   return true;
 }
 

@@ -124,14 +124,26 @@ __device__ __forceinline__ void vp_round_inverse(uint32_t& L, uint32_t& R, uint3
 
 // Decrypts ITEMS independent blocks (L < 2^w, R < 2^r), rounds in reverse,
 // interleaved like vp_encrypt.  keys[0..rounds) are masked to the half width.
+// Two rounds per loop step (an odd round count takes its last round first):
+// with one round per step every state register is rewritten while its old
+// value is still live, which costs a register copy per block and round.
 template <bool ODD, int ITEMS>
 __device__ __forceinline__ void vp_decrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[ITEMS], const CipherShape& cs,
                                            uint32_t rounds, const uint32_t* __restrict__ keys) {
   const uint32_t wmask24 = cs.wmask & 0xFFFFFFu;
-  for (uint32_t rr = rounds; rr-- > 0;) {
+  uint32_t rr = rounds;
+  if (rr & 1u) {
+    --rr;
     const uint32_t key = keys[rr];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) vp_round_inverse<ODD>(L[j], R[j], key, cs.w, wmask24);
+  }
+  for (; rr != 0; rr -= 2) {
+    const uint32_t k1 = keys[rr - 1], k0 = keys[rr - 2];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) vp_round_inverse<ODD>(L[j], R[j], k1, cs.w, wmask24);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) vp_round_inverse<ODD>(L[j], R[j], k0, cs.w, wmask24);
   }
 }
 

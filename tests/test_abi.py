@@ -320,8 +320,10 @@ def test_noalloc_argument_checks():
 
 
 def test_staged_scratch_sizes_and_argument_checks():
-    # n = 2^27 + 1 uint32: k = 28, windows of 2^14, two passes of 7 digit bits
-    want = 512 + 2 * (1 << 16) + 4 * (1 << 30)
+    # n = 2^27 + 1 uint32: k = 28, windows of 2^14, two passes of 7 digit bits;
+    # bucket arrays of 2^28 entries: 4-byte indices and records, then 2-byte
+    # window indices and records
+    want = 512 + 2 * (1 << 16) + (1 << 28) * (4 + 4 + 2 + 4)
     assert B.bs_staged_scratch_bytes((1 << 27) + 1, 4) == want
     assert B.bs_staged_scratch_bytes(0, 4) == 0
     assert B.bs_staged_scratch_bytes(1000, 3) == 0
@@ -338,3 +340,40 @@ def test_staged_scratch_sizes_and_argument_checks():
     assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 65, 1 << 42, need, None) == B.BS_EINVAL
     assert f(FAKE_IN, FAKE_OUT, (1 << 32) + 1, 4, 1, 24, 1 << 42, 1 << 40, None) == B.BS_EINVAL
     assert f(FAKE_IN, FAKE_OUT, 0, 4, 1, 24, None, 0, None) == B.BS_OK
+
+
+def test_staged_workspace_bytes_and_policy():
+    n = (1 << 27) + 1
+    fused = B.bs_workspace_bytes(n, 0, 4)
+    assert B.bs_workspace_bytes_staged(n, 4) == ((fused + 255) // 256) * 256 + B.bs_staged_scratch_bytes(n, 4)
+    # sizes the staged form does not cover: just the fused workspace
+    assert B.bs_workspace_bytes_staged((1 << 32) + 1, 4) == B.bs_workspace_bytes((1 << 32) + 1, 0, 4)
+    assert B.bs_workspace_bytes_staged(n, 3) == 0
+    assert B.bs_probe_set_staged_policy(3) == B.BS_EINVAL
+    for mode in (0, 1, 2):
+        assert B.bs_probe_set_staged_policy(mode) == B.BS_OK
+
+
+def test_staged_table_lines(tmp_path):
+    """A "staged" line makes bs_query_config report the staged form for that
+    class; saving keeps it; a malformed staged line is rejected."""
+    from paper_2106_06161_amd import autotune
+
+    t = tmp_path / "t.txt"
+    t.write_text("arch gfx950\nrounds 24\n0 4 28 16 16 9 1\nstaged 4 28 1 1.7 2.4\nstaged 8 28 0\n")
+    try:
+        assert B.bs_load_tuned_configs(str(t)) == B.BS_OK
+        assert B.bs_query_config(0, 4, (1 << 27) + 1) == (0, 0, B.DEPTH_STAGED, 0)
+        assert B.bs_query_config(0, 8, (1 << 27) + 1)[2] != B.DEPTH_STAGED
+        out = tmp_path / "out.txt"
+        assert B.bs_save_tuned_configs(str(out)) == B.BS_OK
+        assert [(e["elem_bytes"], e["size_bits"], e["prefer"]) for e in autotune.read_staged(str(out))] == [
+            (4, 28, True), (8, 28, False)]
+        assert B.bs_probe_set_staged_policy(0) == B.BS_OK
+        assert B.bs_query_config(0, 4, (1 << 27) + 1)[2] != B.DEPTH_STAGED
+        bad = tmp_path / "bad.txt"
+        bad.write_text("staged 4 28 2\n")
+        assert B.bs_load_tuned_configs(str(bad)) == B.BS_EINVAL
+    finally:
+        B.bs_probe_set_staged_policy(2)
+        assert B.bs_load_tuned_configs(B.TUNED_FILE) == B.BS_OK

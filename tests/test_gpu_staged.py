@@ -134,3 +134,30 @@ def test_staged_argument_errors_on_device():
     # scratch overlapping the output
     assert B.bs_shuffle_staged(x.data_ptr(), big.data_ptr(), 1 << 18, 4, 1, 24, big.data_ptr(), need,
                                sp) == B.BS_EALIAS
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_bs_shuffle_with_room_for_the_staged_form(mode):
+    """bs_shuffle with a workspace of bs_workspace_bytes_staged: policy 1 takes
+    the staged form, 0 the fused kernel, 2 what the shipped table says; the
+    bytes are the oracle's every time, also after a call with a fused-size
+    workspace on the same buffers."""
+    n = (1 << 23) + 1
+    x_np = records(n, 4, seed=21)
+    x = to_dev(x_np)
+    want = oracle.shuffle(x_np, 5, 24)
+    ws = bs.make_workspace(bs.workspace_bytes(n, staged=True), device=DEV)
+    small = bs.make_workspace(bs.workspace_bytes(n), device=DEV)
+    assert B.bs_probe_set_staged_policy(mode) == B.BS_OK
+    try:
+        if mode == 1:
+            assert B.bs_query_config(0, 4, n)[2] == B.DEPTH_STAGED
+        if mode == 0:
+            assert B.bs_query_config(0, 4, n)[2] != B.DEPTH_STAGED
+        for w in (ws, small, ws):
+            y = bs.shuffle(x, 5, 24, workspace=w)
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy().view(np.uint32), want)
+        assert bs.workspace_error(ws) == B.BS_OK and bs.workspace_error(small) == B.BS_OK
+    finally:
+        B.bs_probe_set_staged_policy(2)
