@@ -54,7 +54,14 @@ KERNEL_SOURCES = [
     "paper_2106_06161_amd/csrc/tile_scan.h",
     "paper_2106_06161_amd/csrc/vphilox_round.h",
     "paper_2106_06161_amd/csrc/kernels.h",
+    "paper_2106_06161_amd/csrc/staged.hip",
 ]
+STAGED_KERNELS = ["bsd::(anonymous namespace)::staged_zero_kernel(bsd::StagedArgs)",
+                  "void bsd::(anonymous namespace)::staged_first_kernel<4, false>(bsd::StagedArgs)",
+                  "void bsd::(anonymous namespace)::staged_second_kernel<4>(bsd::StagedArgs)",
+                  "bsd::(anonymous namespace)::staged_scan_kernel(bsd::StagedArgs)",
+                  "void bsd::(anonymous namespace)::staged_place_kernel<4>(bsd::StagedArgs)"]
+DEPTH_STAGED = 16
 
 
 def kernel_source_digest() -> str:
@@ -66,7 +73,10 @@ def kernel_source_digest() -> str:
 
 
 def kernel_label(launch: dict) -> str:
-    """The fused kernel that runs the headline step (even k, 32-bit indices)."""
+    """The kernels that run the headline step (even k, 32-bit indices): the
+    staged form's passes, or the fused kernel."""
+    if launch["depth"] == DEPTH_STAGED:
+        return " + ".join(STAGED_KERNELS)
     if launch["depth"] in (8, 9):  # kept images compacted through LDS (9: pipelined cipher)
         pipe = "true" if launch["depth"] == 9 else "false"
         return "bsd::shuffle_compact_kernel<4, false, {waves}, {items}, ".format(**launch) + pipe + ", 0, true, false>"
@@ -170,33 +180,43 @@ def traffic_record(paths: list) -> dict:
     copy_bytes = ((N_HEADLINE * 4) // 16) * 16
 
     def is_main(name):
-        return "shuffle_compact_kernel" in name or "shuffle_single_kernel" in name
+        return "shuffle_compact_kernel" in name or "shuffle_single_kernel" in name or "::staged_" in name
 
     def rows(d, pattern):
         with open(glob.glob(os.path.join(d, pattern))[0]) as fh:
             return list(csv.DictReader(fh))
 
+    # the step's kernels: one fused kernel, or the staged form's passes (each
+    # launched once per step); per-kernel averages are summed over the step
     main_rows = [r for r in rows(kt, "*kernel_stats.csv") if is_main(r["Name"])]
-    if len(main_rows) != 1:
-        raise SystemExit(f"expected one shuffle kernel in the trace, found {[r['Name'] for r in main_rows]}")
-    mr = main_rows[0]
+    if not main_rows:
+        raise SystemExit("no shuffle kernel in the trace")
+    calls = {int(r["Calls"]) for r in main_rows}
+    if len(calls) != 1:
+        raise SystemExit(f"the step's kernels ran different numbers of times: {[(r['Name'], r['Calls']) for r in main_rows]}")
 
     def counter(d, name):
         rs = rows(d, "*counter_collection.csv")
         copy = [float(r["Counter_Value"]) for r in rs if "copy16_kernel" in r["Kernel_Name"] and r["Counter_Name"] == name]
-        kern = [float(r["Counter_Value"]) for r in rs if is_main(r["Kernel_Name"]) and r["Counter_Name"] == name]
-        return copy, kern
+        per = {}
+        for r in rs:
+            if is_main(r["Kernel_Name"]) and r["Counter_Name"] == name:
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return copy, per
+
+    def per_step(per):
+        return sum(sum(v) / len(v) for v in per.values())
 
     fc, fk = counter(fetch_dir, "FETCH_SIZE")
     wc, wk = counter(write_dir, "WRITE_SIZE")
     fscale = copy_bytes / (fc[0] * 1024.0)
     wscale = copy_bytes / (wc[0] * 1024.0)
-    fetch = sum(fk) / len(fk) * 1024.0 * fscale
-    write = sum(wk) / len(wk) * 1024.0 * wscale
+    fetch = per_step(fk) * 1024.0 * fscale
+    write = per_step(wk) * 1024.0 * wscale
     with open(bench_json) as fh:
         launch = json.loads(fh.read().strip().splitlines()[-1])["config"]["launch"]
     rec = {
-        "kernel": mr["Name"],
+        "kernel": " + ".join(r["Name"] for r in main_rows),
         "workload": "n=2^27+1 uint32, seed 7, 24 rounds, domain 2^28",
         "kernel_source_digest": kernel_source_digest(),
         "fetch_bytes_per_launch": fetch,
@@ -207,10 +227,13 @@ def traffic_record(paths: list) -> dict:
         "copy_probe_bytes": copy_bytes,
         "copy_fetch_kib": fc[0],
         "copy_write_kib": wc[0],
-        "kernel_fetch_kib_avg": sum(fk) / len(fk),
-        "kernel_write_kib_avg": sum(wk) / len(wk),
-        "kernel_avg_ms_rocprof": float(mr["AverageNs"]) / 1e6,
-        "kernel_calls_rocprof": int(mr["Calls"]),
+        "kernel_fetch_kib_avg": per_step(fk),
+        "kernel_write_kib_avg": per_step(wk),
+        "kernel_avg_ms_rocprof": sum(float(r["AverageNs"]) for r in main_rows) / 1e6,
+        "kernel_calls_rocprof": calls.pop(),
+        "per_kernel_ms_rocprof": {r["Name"]: float(r["AverageNs"]) / 1e6 for r in main_rows},
+        "per_kernel_fetch_bytes": {k: sum(v) / len(v) * 1024.0 * fscale for k, v in fk.items()},
+        "per_kernel_write_bytes": {k: sum(v) / len(v) * 1024.0 * wscale for k, v in wk.items()},
         "launch": launch,
     }
     if sq:
@@ -218,12 +241,13 @@ def traffic_record(paths: list) -> dict:
                      "SQ_WAVES", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE"):
             _, v = counter(sq, name)
             if v:
-                rec[name.lower() + "_per_launch"] = sum(v) / len(v)
+                rec[name.lower() + "_per_launch"] = per_step(v)
     if tcc:
-        for name in ("TCC_EA0_RDREQ_sum", "TCC_EA0_WRREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum"):
+        for name in ("TCC_EA0_RDREQ_sum", "TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_RDREQ_LEVEL_sum",
+                     "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum"):
             c, v = counter(tcc, name)
             if v:
-                rec[name.lower() + "_per_launch"] = sum(v) / len(v)
+                rec[name.lower() + "_per_launch"] = per_step(v)
             if c:
                 rec[name.lower() + "_copy"] = c[0]
     return rec
@@ -402,14 +426,15 @@ def bench_batched(torch, bs, W, np, dev, stream, timer, rounds) -> dict:
     }
 
 
-def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None, ws=None) -> dict:
+def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None) -> dict:
     """One shuffle of n uint32 values in each fusion form; every form's output
     is checked equal to the fused kernel's."""
     sp = stream.cuda_stream
     if x is None:
         x = torch.from_numpy(W.uniform_u32(n, seed=SEED)).to(dev)
         y = torch.empty_like(x)
-        ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+    # a workspace with no room for the staged form: bs_shuffle runs the fused kernel
+    ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
     ref = torch.empty_like(x)
     scratch = torch.empty(B.bs_probe_unfused_scratch_bytes(n), dtype=torch.uint8, device=dev)
 
@@ -554,53 +579,53 @@ def bench_footprint(torch, B, dev, stream, timer) -> list:
 
 def bench_large(torch, bs, B, dev, stream, timer, rounds) -> dict:
     """n = 10^9 uint32 arange (seed 1, domain 2^30) and 2.5e8 records of four
-    float32 (seeded device normal values, seed 11, domain 2^28), each beside
-    the random-read ceiling over the same footprint (4 GiB) and record size."""
+    float32 (seeded device normal values, seed 11, domain 2^28): bs_shuffle as
+    a caller gets it (a workspace with room for the staged form; the tuned
+    table picks the form), and each form explicitly, beside the random-read
+    ceiling over the same footprint (4 GiB) and record size."""
     sp = stream.cuda_stream
     res = {}
     probe = torch.zeros(1 << 30, dtype=torch.int32, device=dev)  # 4 GiB
     for name, eb in (("u32", 4), ("rec16", 16)):
         res[f"ceiling_{name}_4GiB_G_reads_s"] = random_read_rate(B, torch, timer, probe, 4 << 30, eb, 1 << 28, sp)
     del probe
-    n = 10**9
-    x = torch.arange(n, dtype=torch.int32, device=dev)
-    y = torch.empty_like(x)
-    ws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
-    t = timer.run(lambda: bs.shuffle(x, 1, rounds, out=y, workspace=ws), 3)
-    res["u32_1e9_ms"] = t * 1e3
-    res["u32_1e9_Gelem_s"] = n / t / 1e9
-    res["u32_1e9_alg_GBps"] = 8.0 * n / t / 1e9
-    res["u32_1e9_pct_of_same_footprint_ceiling"] = 100.0 * res["u32_1e9_Gelem_s"] / res["ceiling_u32_4GiB_G_reads_s"]
-    res["u32_1e9_launch"] = list(B.bs_query_config(0, 4, n))
-    st_scratch = torch.empty(bs.staged_scratch_bytes(n, 4), dtype=torch.uint8, device=dev)
-    ref = y.clone()
-    t = timer.run(lambda: bs.shuffle_staged(x, 1, rounds, out=y, scratch=st_scratch), 3)
-    if not torch.equal(y, ref):
-        raise RuntimeError("the staged form differs from the fused kernel at n=10^9")
-    res["u32_1e9_staged_ms"] = t * 1e3
-    res["u32_1e9_staged_Gelem_s"] = n / t / 1e9
-    del x, y, ref, st_scratch
-    n = 250_000_000
-    gen = torch.Generator(device=dev).manual_seed(11)
-    x = torch.randn((n, 4), dtype=torch.float32, device=dev, generator=gen)
-    y = torch.empty_like(x)
-    t = timer.run(lambda: bs.shuffle(x, 11, rounds, out=y, workspace=ws), 3)
-    res["rec16_2p5e8_ms"] = t * 1e3
-    res["rec16_2p5e8_Gelem_s"] = n / t / 1e9
-    res["rec16_2p5e8_alg_GBps"] = 32.0 * n / t / 1e9
-    res["rec16_2p5e8_pct_of_same_footprint_ceiling"] = (100.0 * res["rec16_2p5e8_Gelem_s"]
-                                                       / res["ceiling_rec16_4GiB_G_reads_s"])
-    res["rec16_2p5e8_launch"] = list(B.bs_query_config(0, 16, n))
-    st_scratch = torch.empty(bs.staged_scratch_bytes(n, 16), dtype=torch.uint8, device=dev)
-    ref = y.clone()
-    t = timer.run(lambda: bs.shuffle_staged(x, 11, rounds, out=y, scratch=st_scratch), 3)
-    if not torch.equal(y, ref):
-        raise RuntimeError("the staged form differs from the fused kernel at 2.5e8 x 16 B")
-    res["rec16_2p5e8_staged_ms"] = t * 1e3
-    res["rec16_2p5e8_staged_Gelem_s"] = n / t / 1e9
-    del x, y, ref, st_scratch
-    if bs.workspace_error(ws) != 0:
-        raise RuntimeError("device-side error in the large workloads")
+    for name, n, make, seed in (("u32_1e9", 10**9, lambda n: torch.arange(n, dtype=torch.int32, device=dev), 1),
+                                ("rec16_2p5e8", 250_000_000,
+                                 lambda n: torch.randn((n, 4), dtype=torch.float32, device=dev,
+                                                       generator=torch.Generator(device=dev).manual_seed(11)), 11)):
+        log(f"bench: large {name}")
+        x = make(n)
+        y = torch.empty_like(x)
+        eb = x.element_size() * (x.numel() // n)
+        ws = bs.make_workspace(bs.workspace_bytes(n, elem_bytes=eb, staged=True), device=dev)
+        t = timer.run(lambda: bs.shuffle(x, seed, rounds, out=y, workspace=ws), 3)
+        ref = y.clone()
+        launch = list(B.bs_query_config(0, eb, n))
+        res[f"{name}_form"] = "staged" if launch[2] == DEPTH_STAGED else "fused"
+        res[f"{name}_launch"] = launch
+        res[f"{name}_ms"] = t * 1e3
+        res[f"{name}_Gelem_s"] = n / t / 1e9
+        res[f"{name}_alg_GBps"] = 2.0 * eb * n / t / 1e9
+        fws = bs.make_workspace(bs.workspace_bytes(n), device=dev)
+        tf = timer.run(lambda: bs.shuffle(x, seed, rounds, out=y, workspace=fws), 3)
+        if not torch.equal(y, ref):
+            raise RuntimeError(f"the fused kernel differs from bs_shuffle's form at {name}")
+        res[f"{name}_fused_ms"] = tf * 1e3
+        ceil = res["ceiling_u32_4GiB_G_reads_s" if eb == 4 else "ceiling_rec16_4GiB_G_reads_s"]
+        res[f"{name}_fused_pct_of_same_footprint_ceiling"] = 100.0 * (n / tf / 1e9) / ceil
+        need = bs.staged_scratch_bytes(n, eb)
+        if need:
+            scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+            ts = timer.run(lambda: bs.shuffle_staged(x, seed, rounds, out=y, scratch=scratch), 3)
+            if not torch.equal(y, ref):
+                raise RuntimeError(f"the staged form differs from bs_shuffle's form at {name}")
+            res[f"{name}_staged_ms"] = ts * 1e3
+            res[f"{name}_staged_Gelem_s"] = n / ts / 1e9
+            del scratch
+        if bs.workspace_error(ws) != 0 or bs.workspace_error(fws) != 0:
+            raise RuntimeError(f"device-side error in the large workload {name}")
+        del x, y, ref, ws, fws
+        torch.cuda.empty_cache()
     return res
 
 
@@ -616,16 +641,17 @@ def bench_sweep(torch, bs, B, dev, stream, timer, rounds, gather: bool = False) 
         for w in range(8, 31):
             x = torch.arange((1 << w) + 1, dtype=torch.int64, device=dev).to(dt)
             y = torch.empty_like(x)
-            ws = bs.make_workspace(bs.workspace_bytes((1 << w) + 1), device=dev)
+            ws = bs.make_workspace(bs.workspace_bytes((1 << w) + 1, elem_bytes=eb, staged=True), device=dev)
             reads = max(1 << 16, ((1 << w) + 15) // 16 * 16)
             ceil = random_read_rate(B, torch, timer, x, (1 << w) * eb, eb, reads, sp)
             for n in (1 << w, (1 << w) + 1):
                 log(f"bench: sweep elem_bytes={eb} n={n}")
                 xs, ys = x[:n], y[:n]
                 t = timer.run(lambda: bs.shuffle(xs, SEED, rounds, out=ys, workspace=ws), 5)
+                launch = list(B.bs_query_config(0, eb, n))
                 row = {"elem_bytes": eb, "n": n, "shuffle_ms": t * 1e3, "Gelem_s": n / t / 1e9,
                        "random_read_ceiling_G_s": ceil, "pct_of_ceiling": 100.0 * (n / t / 1e9) / ceil,
-                       "launch": list(B.bs_query_config(0, eb, n))}
+                       "form": "staged" if launch[2] == DEPTH_STAGED else "fused", "launch": launch}
                 if gather:
                     idx = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
                     tg = timer.run(lambda: B.bs_probe_gather(xs.data_ptr(), n, ys.data_ptr(), idx.data_ptr(), n,
@@ -636,6 +662,7 @@ def bench_sweep(torch, bs, B, dev, stream, timer, rounds, gather: bool = False) 
             if bs.workspace_error(ws) != 0:
                 raise RuntimeError("device-side error in the sweep")
             del x, y, ws
+            torch.cuda.empty_cache()
     return out
 
 
@@ -760,7 +787,9 @@ def main() -> int:
     x_np = W.uniform_u32(N_HEADLINE, seed=SEED)
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
-    ws = bs.make_workspace(bs.workspace_bytes(N_HEADLINE), device=dev)
+    # the product call: bs_shuffle with room for either form (it takes the
+    # staged form where the tuned table prefers it)
+    ws = bs.make_workspace(bs.workspace_bytes(N_HEADLINE, staged=True), device=dev)
 
     if args.profile:
         nb = (N_HEADLINE * 4) // 16 * 16
@@ -801,6 +830,7 @@ def main() -> int:
     achieved = alg_bytes / kernel_s / 1e9
     digest = kernel_source_digest()
     launch = dict(zip(("waves", "items", "depth", "grid_mult"), B.bs_query_config(0, 4, N_HEADLINE)))
+    form = "staged" if launch["depth"] == DEPTH_STAGED else "fused"
     traffic = committed_traffic(digest, launch)
     result = {
         "metric": "Gelem/s + % HBM peak at n=2^27+1 u32; batched vs per-call; p99 latency",
@@ -819,7 +849,7 @@ def main() -> int:
             "workload": "single bijective shuffle, n=2^27+1 uint32 uniform (PCG64 seed 7), seed 7, "
                         f"{rounds} rounds, domain 2^28",
             "n": N_HEADLINE, "elem_bytes": 4, "rounds": rounds, "seed": SEED,
-            "launch": launch,
+            "launch": launch, "form": form,
         },
         "pct_hbm_peak": 100.0 * (alg_bytes * args.steps / wall / 1e9) / HBM_PEAK_GBPS,
         "roofline": {
@@ -890,7 +920,7 @@ def main() -> int:
 
     if not args.no_fusion:
         log("bench: fusion forms at the headline size (fused, two-pass scan, unfused, LCG)")
-        result["fusion"] = bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, N_HEADLINE, x, y, ws)
+        result["fusion"] = bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, N_HEADLINE, x, y)
         if args.fusion_sweep:
             sweep = []
             for bits in range(20, 30):

@@ -371,7 +371,12 @@ class HipExecutor:
         self.reserve_bytes = reserve_bytes
         self.streams = [torch.cuda.Stream(self.device) for _ in range(streams)]
         self.next_stream = 0
-        ws_bytes = max(bs.workspace_bytes(pool_items), bs.workspace_bytes(batch_items, batch_requests))
+        # room for the staged form of the largest request of either element
+        # size (bs_shuffle takes it where the tuned table prefers it) and for
+        # the largest coalesced batch
+        ws_bytes = max(bs.workspace_bytes(pool_items, elem_bytes=4, staged=True),
+                       bs.workspace_bytes(pool_items, elem_bytes=8, staged=True),
+                       bs.workspace_bytes(batch_items, batch_requests))
         self.workspaces = [bs.make_workspace(ws_bytes, device=self.device, stream=s) for s in self.streams]
         self.status = torch.full((4096,), -1, dtype=torch.int32).pin_memory()
         self.next_slot = 0

@@ -144,9 +144,17 @@ def test_shipped_tuned_table_is_valid():
     for e in entries:
         assert (e["waves"], e["items"], e["depth"]) in shapes and e["grid_mult"] in autotune.GRIDS
     assert B.bs_load_tuned_configs(B.TUNED_FILE) == B.BS_OK
-    # the table decides the launch shape the library reports
+    # the table decides the form and launch shape the library reports
     e = next(e for e in entries if e["kind"] == 0 and e["elem_bytes"] == 4 and e["size_bits"] == 28)
-    assert B.bs_query_config(0, 4, (1 << 27) + 1) == (e["waves"], e["items"], e["depth"], e["grid_mult"])
+    staged = {(t["elem_bytes"], t["size_bits"]): t["prefer"] for t in autotune.read_staged()}
+    if staged.get((4, 28)):
+        assert B.bs_query_config(0, 4, (1 << 27) + 1) == (0, 0, B.DEPTH_STAGED, 0)
+    else:
+        assert B.bs_query_config(0, 4, (1 << 27) + 1) == (e["waves"], e["items"], e["depth"], e["grid_mult"])
+    # 16-byte records stay with the fused kernel at 2^28
+    e16 = next(e for e in entries if e["kind"] == 0 and e["elem_bytes"] == 16 and e["size_bits"] == 28)
+    if not staged.get((16, 28)):
+        assert B.bs_query_config(0, 16, 250_000_000) == (e16["waves"], e16["items"], e16["depth"], e16["grid_mult"])
 
 
 def test_tuned_table_files_round_trip(tmp_path):

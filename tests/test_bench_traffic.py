@@ -72,3 +72,28 @@ def test_record_is_used_only_for_matching_sources_and_shape(runs, tmp_path, monk
     assert bench.committed_traffic(digest, LAUNCH)["hbm_bytes_per_launch"] == rec["hbm_bytes_per_launch"]
     assert bench.committed_traffic("0" * 16, LAUNCH) is None
     assert bench.committed_traffic(digest, dict(LAUNCH, grid_mult=0)) is None
+
+
+def test_traffic_record_sums_the_staged_passes(tmp_path):
+    """A staged step runs several kernels once each: the record sums their
+    per-launch averages (time, FETCH, WRITE)."""
+    names = ["void bsd::(anonymous namespace)::staged_first_kernel<4, false>(bsd::StagedArgs)",
+             "void bsd::(anonymous namespace)::staged_second_kernel<4>(bsd::StagedArgs)",
+             "void bsd::(anonymous namespace)::staged_place_kernel<4>(bsd::StagedArgs)"]
+    kt = str(tmp_path / "kt")
+    _write(os.path.join(kt, "kt_kernel_stats.csv"), ["Name", "Calls", "AverageNs"],
+           [[names[0], 5, 800_000.0], [names[1], 5, 500_000.0], [names[2], 5, 400_000.0], [COPY, 1, 1.0]])
+    copy_bytes = ((bench.N_HEADLINE * 4) // 16) * 16
+    for d, name, scale in (("fetch", "FETCH_SIZE", 2), ("write", "WRITE_SIZE", 1)):
+        rows = [[COPY, name, copy_bytes / scale / 1024]]
+        rows += [[nm, name, 100.0 * (i + 1)] for i, nm in enumerate(names) for _ in range(2)]
+        _write(os.path.join(str(tmp_path / d), "x_counter_collection.csv"),
+               ["Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    js = tmp_path / "kt.json"
+    launch = {"waves": 0, "items": 0, "depth": 16, "grid_mult": 0}
+    js.write_text(json.dumps({"config": {"launch": launch}}) + "\n")
+    rec = bench.traffic_record([kt, str(tmp_path / "fetch"), str(tmp_path / "write"), str(js)])
+    assert rec["kernel_avg_ms_rocprof"] == pytest.approx(1.7)
+    assert rec["fetch_bytes_per_launch"] == pytest.approx((100 + 200 + 300) * 1024 * 2.0)
+    assert rec["write_bytes_per_launch"] == pytest.approx((100 + 200 + 300) * 1024 * 1.0)
+    assert len(rec["per_kernel_ms_rocprof"]) == 3 and rec["launch"] == launch

@@ -41,6 +41,8 @@ def test_device_error_fails_only_its_launch():
 
     ex = HipExecutor(streams=2, rounds=24, pool_items=1 << 22)
     srv = ShuffleServer(ex, budget_bytes=256 << 20, small_items=1 << 10, max_inflight=4)
+    # the fused kernel (the form with a look-back) for every request
+    assert B.bs_probe_set_staged_policy(0) == B.BS_OK
     try:
         first = srv.run(make_requests(20, 100_000, 1_000_000, qps=1e4, seed=3))
         assert len(first.ok()) == 20
@@ -49,6 +51,7 @@ def test_device_error_fails_only_its_launch():
         torch.cuda.synchronize()
     finally:
         B.bs_probe_set_watchdog(0, 0)
+        B.bs_probe_set_staged_policy(2)
     assert bad.completions and not bad.ok()
     assert all("BS_ETIMEOUT" in c.error for c in bad.completions)
     rs = make_requests(20, 100_000, 1_000_000, qps=1e4, seed=5)
