@@ -542,10 +542,26 @@ def bench_small(torch, bs, dev, timer) -> dict:
             B._check(B.bs_probe_copy(x.data_ptr(), y.data_ptr(), 16, side.cuda_stream), "bs_probe_copy")
     torch.cuda.synchronize()
     t_floor = timer.run(g2.replay, 20, warm=3) / calls
+    # dependent device-scope round trips inside a 32-workgroup launch (the
+    # small shuffle's tile count): launches of 0, 1, 2, 4 and 8 chained
+    # atomics per workgroup, 100 per graph
+    words = torch.zeros(128, dtype=torch.int32, device=dev)
+    trips = {}
+    for chain in (0, 1, 2, 4, 8):
+        g3 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g3, stream=side):
+            for _ in range(calls):
+                B._check(B.bs_probe_round_trips(words.data_ptr(), 32, chain, side.cuda_stream),
+                         "bs_probe_round_trips")
+        torch.cuda.synchronize()
+        trips[chain] = timer.run(g3.replay, 20, warm=3) / calls * 1e6
+        del g3
     del g, g2
     return {"workload": "n=100,000 uint32 arange, seed 42, 4 rounds, domain 2^17", "us_per_call": t * 1e6,
             "Gelem_s": n / t / 1e9, "us_per_call_graph": t_graph * 1e6, "Gelem_s_graph": n / t_graph / 1e9,
-            "graph_launch_floor_us": t_floor * 1e6}
+            "graph_launch_floor_us": t_floor * 1e6,
+            "round_trip_launch_us_by_chain": trips,
+            "round_trip_us": (trips[8] - trips[0]) / 8}
 
 
 FOOTPRINTS_MIB = [32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]
@@ -910,6 +926,19 @@ def main() -> int:
         tp = timer.run(lambda: bs.shuffle(xp, SEED, rounds, out=yp, workspace=ws), 10)
         ceil["shuffle_pow2_n2p27_ms"] = tp * 1e3
         ceil["shuffle_pow2_n2p27_Gelem_s"] = (1 << 27) / tp / 1e9
+        # integer VALU issue rates (the cipher's instructions): SIMD cycles per
+        # wave instruction at 2.4 GHz over 1,024 SIMDs; 4 is one wave64
+        # instruction per 4 cycles on a 16-lane SIMD (full rate)
+        groups, iters = 2048, 4096
+        sink = torch.empty(groups * 256, dtype=torch.int32, device=dev)
+        rates = {}
+        for op, name in enumerate(("v_xor_b32", "v_mul_u32_u24", "v_mad_u32_u24", "v_mul_lo_u32", "v_mul_hi_u32",
+                                   "v_mad_u64_u32+v_xor_b32")):
+            t = timer.run(lambda: B._check(B.bs_probe_int_rate(op, iters, sink.data_ptr(), groups, sp),
+                                           "bs_probe_int_rate"), 5)
+            rates[name] = t * 2.4e9 * 1024 / (groups * 4 * iters * 8)
+        del sink
+        ceil["int_valu_cycles_per_wave_instruction"] = rates
         ceil["shuffle_pct_of_copy"] = 100.0 * achieved / ceil["copy_GBps"]
         ceil["shuffle_pct_of_gather"] = 100.0 * ceil["gather_index_array_ms"] / (kernel_s * 1e3)
         ceil["shuffle_pct_of_random_read_rate"] = 100.0 * (N_HEADLINE / kernel_s / 1e9) / ceil["random_reads_512MiB_G_s"]

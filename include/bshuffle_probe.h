@@ -42,6 +42,27 @@ bs_status bs_probe_random_reads(const void *in, uint64_t words, void *out, uint3
 bs_status bs_probe_random_reads_region(const void *in, uint64_t region_bytes, uint32_t elem_bytes, uint64_t reads,
                                        void *out, uint32_t salt, void *stream);
 
+/* Dependent round trips: `groups` workgroups of 64 lanes; lane 0 of each runs
+ * `chain` device-scope atomic adds on words[0..64) in sequence (each address
+ * depends on the previous result), then stores the last result in
+ * words[64..128).  words: device memory of at least 128 uint32.  groups in
+ * [1, 65536], chain <= 1024 (BS_EINVAL otherwise).  Timing it against `chain`
+ * measures what one dependent global round trip costs a small launch (the
+ * ticket, look-back and completion counters of a small shuffle are such
+ * steps). */
+bs_status bs_probe_round_trips(uint32_t *words, uint32_t groups, uint32_t chain, void *stream);
+
+/* Issue rate of one integer VALU instruction: `groups` workgroups of 256
+ * lanes, eight independent chains per lane of `iters` instructions each;
+ * op 0 v_xor_b32, 1 v_mul_u32_u24, 2 v_mad_u32_u24, 3 v_mul_lo_u32,
+ * 4 v_mul_hi_u32, 5 v_mad_u64_u32 (plus a v_xor_b32 of its result words).
+ * out: device memory of groups * 256 uint32 (one word per lane, written so
+ * the chains are not dropped).  groups in [1, 65536], iters in [1, 2^20],
+ * op <= 5 (BS_EINVAL otherwise).  Timing a launch gives the cycles one wave
+ * instruction of that kind holds a SIMD: the cipher's cost per round
+ * (vp_round, vp_round_inverse) is counted in such instructions. */
+bs_status bs_probe_int_rate(uint32_t op, uint32_t iters, uint32_t *out, uint32_t groups, void *stream);
+
 /* Random gather with an index array: out[j] = in[idx[j]] for j < n, records
  * of elem_bytes (1,2,4,8,16); idx is a device uint32 array whose entries must
  * be < n_in (checked on the device: an out-of-range index is skipped). */

@@ -74,6 +74,8 @@ _SIGNATURES = {
     "bs_probe_gather": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _vp]),
     "bs_probe_random_reads": (_i32, [_vp, _u64, _vp, _u32, _vp]),
     "bs_probe_random_reads_region": (_i32, [_vp, _u64, _u32, _u64, _vp, _u32, _vp]),
+    "bs_probe_round_trips": (_i32, [_vp, _u32, _u32, _vp]),
+    "bs_probe_int_rate": (_i32, [_u32, _u32, _vp, _u32, _vp]),
     "bs_probe_cipher_scan": (_i32, [_u64, _u64, _u32, _vp, _sz, _vp]),
     "bs_probe_set_store_mode": (_i32, [_u32]),
     "bs_probe_set_xcd_mode": (_i32, [_u32]),
@@ -562,3 +564,11 @@ def bs_workspace_bytes_staged(n: int, elem_bytes: int) -> int:
 
 def bs_probe_set_staged_policy(mode: int) -> int:
     return int(lib().bs_probe_set_staged_policy(mode))
+
+
+def bs_probe_round_trips(words_ptr, groups, chain, stream) -> int:
+    return int(lib().bs_probe_round_trips(words_ptr, groups, chain, stream))
+
+
+def bs_probe_int_rate(op, iters, out_ptr, groups, stream) -> int:
+    return int(lib().bs_probe_int_rate(op, iters, out_ptr, groups, stream))

@@ -78,6 +78,50 @@ __global__ __launch_bounds__(256) void random_reads_kernel(const T* __restrict__
   out[t] = sum;
 }
 
+// Dependent round trips to device-coherent memory: lane 0 of every workgroup
+// performs `chain` device-scope atomic adds in sequence, each address taken
+// from the previous result (so none can start before the previous one
+// returns), then stores the last result.  Timing launches of it against
+// `chain` gives the cost of one round trip inside a small launch.
+__global__ void round_trip_kernel(uint32_t* __restrict__ words, uint32_t chain) {
+  if (threadIdx.x != 0) return;
+  uint32_t x = 0;
+  // x >> 31 is 0 for these counts, but the compiler cannot know it
+  for (uint32_t i = 0; i < chain; ++i) x = atomicAdd(&words[(x >> 31) + blockIdx.x % 64u], 1u);
+  words[64 + blockIdx.x % 64u] = x;
+}
+
+// Issue rate of one VALU instruction: 256 lanes per workgroup, eight
+// independent chains per lane, `iters` instructions per chain, written in
+// asm so the compiler neither fuses nor reorders them.  op: 0 v_xor_b32,
+// 1 v_mul_u32_u24, 2 v_mad_u32_u24, 3 v_mul_lo_u32, 4 v_mul_hi_u32,
+// 5 v_mad_u64_u32 (each followed by a v_xor_b32 of its two result words).
+template <int OP>
+__global__ __launch_bounds__(256) void int_rate_kernel(uint32_t* __restrict__ out, uint32_t iters, uint32_t c) {
+  uint32_t a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = threadIdx.x * 8u + uint32_t(j) + blockIdx.x;
+  for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if constexpr (OP == 0) asm volatile("v_xor_b32 %0, %1, %0" : "+v"(a[j]) : "s"(c));
+      if constexpr (OP == 1) asm volatile("v_mul_u32_u24 %0, %1, %0" : "+v"(a[j]) : "s"(c));
+      if constexpr (OP == 2) asm volatile("v_mad_u32_u24 %0, %1, %0, %0" : "+v"(a[j]) : "s"(c));
+      if constexpr (OP == 3) asm volatile("v_mul_lo_u32 %0, %1, %0" : "+v"(a[j]) : "s"(c));
+      if constexpr (OP == 4) asm volatile("v_mul_hi_u32 %0, %1, %0" : "+v"(a[j]) : "s"(c));
+      if constexpr (OP == 5) {
+        uint64_t p, carry;
+        asm volatile("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(p), "=s"(carry) : "s"(c), "v"(a[j]));
+        a[j] = uint32_t(p) ^ uint32_t(p >> 32);
+      }
+    }
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x ^= a[j];
+  out[blockIdx.x * 256u + threadIdx.x] = x;
+}
+
 int32_t g_probe_hip_error = 0;
 
 }  // namespace
@@ -147,6 +191,39 @@ bs_status bs_probe_random_reads_region(const void* in, uint64_t region_bytes, ui
                          lanes, salt);
       break;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_probe_hip_error = int32_t(e);
+    return BS_EHIP;
+  }
+  return BS_OK;
+}
+
+bs_status bs_probe_int_rate(uint32_t op, uint32_t iters, uint32_t* out, uint32_t groups, void* stream) {
+  if (!out || groups == 0 || groups > 65536 || iters == 0 || iters > (1u << 20) || op > 5) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(out) % 4) return BS_EELEM;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t c = 0x9E3779u;  // 24-bit multiplier: the 24-bit forms see the same operand
+  switch (op) {
+    case 0: hipLaunchKernelGGL(int_rate_kernel<0>, dim3(groups), dim3(256), 0, st, out, iters, c); break;
+    case 1: hipLaunchKernelGGL(int_rate_kernel<1>, dim3(groups), dim3(256), 0, st, out, iters, c); break;
+    case 2: hipLaunchKernelGGL(int_rate_kernel<2>, dim3(groups), dim3(256), 0, st, out, iters, c); break;
+    case 3: hipLaunchKernelGGL(int_rate_kernel<3>, dim3(groups), dim3(256), 0, st, out, iters, c); break;
+    case 4: hipLaunchKernelGGL(int_rate_kernel<4>, dim3(groups), dim3(256), 0, st, out, iters, c); break;
+    default: hipLaunchKernelGGL(int_rate_kernel<5>, dim3(groups), dim3(256), 0, st, out, iters, c); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_probe_hip_error = int32_t(e);
+    return BS_EHIP;
+  }
+  return BS_OK;
+}
+
+bs_status bs_probe_round_trips(uint32_t* words, uint32_t groups, uint32_t chain, void* stream) {
+  if (!words || groups == 0 || groups > 65536 || chain > 1024) return BS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(words) % 4) return BS_EELEM;
+  hipLaunchKernelGGL(round_trip_kernel, dim3(groups), dim3(64), 0, static_cast<hipStream_t>(stream), words, chain);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     g_probe_hip_error = int32_t(e);

@@ -41,24 +41,34 @@ constexpr uint32_t kScanThreads = 1024;
 // record tiles with several workgroups per CU.
 template <int EB, int PASS>
 struct DistShape {
-  static constexpr uint32_t kThreads = PASS == 1 ? 1024u : (EB <= 4 ? 256u : EB == 8 ? 512u : 1024u);
-  static constexpr uint32_t kTile = PASS == 1 ? (EB <= 4 ? 16384u : EB == 8 ? 8192u : 4096u) : 4096u;
+  static constexpr uint32_t kThreads = PASS == 1 ? 1024u : (EB <= 8 ? 512u : 1024u);
+  static constexpr uint32_t kTile = PASS == 1 ? (EB <= 4 ? 16384u : EB == 8 ? 8192u : 4096u) : (EB <= 4 ? 8192u : 4096u);
   static constexpr uint32_t kItems = kTile / kThreads;
   static constexpr uint32_t kDigitsPerThread = (kMaxDigits + kThreads - 1) / kThreads;
 };
 constexpr uint32_t kMaxFirstTile = 16384;
+
+// Inclusive scan over the 64 lanes of a wavefront with DPP moves (no LDS
+// traffic, no lane-address registers): shifts by 1, 2, 4 and 8 within each
+// row of 16 lanes, then lane 15 of each row added into the next row and lane
+// 31 into the upper half.  Lanes whose DPP source is outside the row, and
+// rows the row mask leaves out, receive the 0 given as the old value.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x111, 0xf, 0xf, false));  // row_shr:1
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x112, 0xf, 0xf, false));  // row_shr:2
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xf, 0xf, false));  // row_shr:4
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xf, 0xf, false));  // row_shr:8
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xa, 0xf, false));  // row_bcast:15, rows 1, 3
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xc, 0xf, false));  // row_bcast:31, rows 2, 3
+  return v;
+}
 
 // Exclusive scan over a workgroup of THREADS threads; *total gets the sum.
 // Uses waves[THREADS / 64] words of LDS; ends with a barrier.
 template <uint32_t THREADS>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* waves, uint32_t* total) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  uint32_t incl = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t t = __shfl_up(incl, off, 64);
-    if (lane >= uint32_t(off)) incl += t;
-  }
+  const uint32_t incl = wave_inclusive_scan(v);
   if (lane == 63) waves[wave] = incl;
   __syncthreads();
   uint32_t before = 0, sum = 0;
@@ -245,7 +255,9 @@ __global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_first_ker
 // 1), appended to window d1 * 2^b2 + digit.  Work item w covers entries
 // [c * tile, (c + 1) * tile) of bucket w / chunks; items past a bucket's
 // count exit at once (about half of them: a bucket holds the kept share of
-// its capacity).
+// its capacity).  Consecutive work items share a bucket, so the workgroups
+// in flight append to the same windows and their runs fill whole lines in
+// L2 before they are written back.
 template <int EB>
 __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_kernel(const StagedArgs a) {
   using S = DistShape<EB, 2>;
@@ -484,7 +496,7 @@ bool staged_digits(uint32_t k, uint32_t elem_bytes, uint32_t* s, uint32_t* b1, u
     *b1 = nb;
     *b2 = 0;
   } else {
-    *b1 = (nb + 1) / 2;
+    *b1 = nb / 2 + 1 < kMaxDigitBits ? nb / 2 + 1 : kMaxDigitBits;
     *b2 = nb - *b1;
   }
   // the second pass reads first-pass buckets in whole distribution tiles

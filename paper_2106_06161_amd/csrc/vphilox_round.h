@@ -97,14 +97,22 @@ __device__ __forceinline__ void vp_encrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[I
 }
 
 // The inverse, by the three steps of Sec. 3.2 applied to one round's output
-// (L', R') in the same layout (R holds r bits, for odd k bit w is the extra
-// bit; R must arrive clean, without bits above r):
+// (L', R') in the same layout (for odd k bit w of R is the extra bit):
 //   B      = bits [1, w] of R' (odd k; bit 0 is the old extra bit) or R'
 //   L      = B^-1(B) = M0^-1 * B mod 2^w
-//   R      = (F(L) ^ L') & wmask, the old extra bit back in bit w
+//   R      = F(L) ^ L' on bits [0, w), the old extra bit back in bit w
 // Only the low w <= 24 bits of M0^-1 * B survive, so one 24-bit multiply
-// (v_mul_u32_u24, full rate) with M0^-1 mod 2^24 gives L; F(L) reuses the
-// forward round's product.  Keys are masked to the half width.
+// (v_mul_u32_u24) with M0^-1 mod 2^24 gives L; F(L) reuses the forward
+// round's product.  Keys are masked to the half width.
+//
+// Bits of R above r (above w for even k) may hold leftovers between rounds:
+// they only reach bits at or above w of the next product M0^-1 * B, which the
+// mask on L drops.  So R is never masked inside the loop, only once at the end
+// of vp_decrypt, and an even-k round is five VALU instructions (24-bit
+// multiply, mask, 32x32 high product, 24-bit multiply-add, three-input xor);
+// odd k adds the shift that extracts B and the two that move the extra bit.
+// The 24-bit multiply is written out: the compiler otherwise proves that a
+// full 32-bit multiply gives the same masked bits and emits v_mul_lo_u32.
 constexpr uint64_t kM0Inverse = 0xF5F365BD212BDF9Bull;
 static_assert(kM0 * kM0Inverse == 1, "kM0Inverse is the inverse of M0 mod 2^64");
 constexpr uint32_t kM0InvLo24 = static_cast<uint32_t>(kM0Inverse) & 0xFFFFFFu;
@@ -112,13 +120,25 @@ constexpr uint32_t kM0InvLo24 = static_cast<uint32_t>(kM0Inverse) & 0xFFFFFFu;
 template <bool ODD>
 __device__ __forceinline__ void vp_round_inverse(uint32_t& L, uint32_t& R, uint32_t key, uint32_t w,
                                                  uint32_t wmask24) {
-  const uint32_t B = ODD ? (R >> 1) : R;  // below 2^w: R is clean
-  const uint32_t Lp = __umul24(kM0InvLo24, B) & wmask24;
+  const uint32_t B = ODD ? (R >> 1) : R;
+  uint32_t t;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(t) : "s"(kM0InvLo24), "v"(B));
+  const uint32_t Lp = t & wmask24;
   const uint64_t p = uint64_t(kM0Lo) * uint64_t(Lp);
   uint32_t hi;
   asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(hi) : "s"(kM0Hi24), "v"(Lp), "v"(uint32_t(p >> 32)));
-  const uint32_t low = (hi ^ key ^ L) & wmask24;
-  R = ODD ? low | ((R & 1u) << w) : low;
+  // low = hi ^ L ^ key as one v_bitop3_b32 (truth table 0x96; the compiler
+  // emits two xors): bits [0, w) are R's, above them leftovers
+  uint32_t low;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(low) : "v"(hi), "v"(L), "s"(key));
+  if constexpr (ODD) {
+    // bits [0, w) from low, the extra bit (bit 0 of R') into bit w: one
+    // shift and one bitfield insert (v_bfi_b32: mask ? low : R << w)
+    const uint32_t Rs = R << w;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(R) : "s"(wmask24), "v"(low), "v"(Rs));
+  } else {
+    R = low;
+  }
   L = Lp;
 }
 
@@ -127,6 +147,7 @@ __device__ __forceinline__ void vp_round_inverse(uint32_t& L, uint32_t& R, uint3
 // Two rounds per loop step (an odd round count takes its last round first):
 // with one round per step every state register is rewritten while its old
 // value is still live, which costs a register copy per block and round.
+// Leaves L < 2^w and R < 2^r.
 template <bool ODD, int ITEMS>
 __device__ __forceinline__ void vp_decrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[ITEMS], const CipherShape& cs,
                                            uint32_t rounds, const uint32_t* __restrict__ keys) {
@@ -145,6 +166,8 @@ __device__ __forceinline__ void vp_decrypt(uint32_t (&L)[ITEMS], uint32_t (&R)[I
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) vp_round_inverse<ODD>(L[j], R[j], k0, cs.w, wmask24);
   }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) R[j] &= cs.rmask;
 }
 
 }  // namespace bsd

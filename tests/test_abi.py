@@ -328,10 +328,10 @@ def test_noalloc_argument_checks():
 
 
 def test_staged_scratch_sizes_and_argument_checks():
-    # n = 2^27 + 1 uint32: k = 28, windows of 2^14, two passes of 7 digit bits;
-    # bucket arrays of 2^28 entries: 4-byte indices and records, then 2-byte
-    # window indices and records
-    want = 512 + 2 * (1 << 16) + (1 << 28) * (4 + 4 + 2 + 4)
+    # n = 2^27 + 1 uint32: k = 28, windows of 2^14, passes of 8 and 6 digit
+    # bits (2^8 bucket counts); bucket arrays of 2^28 entries: 4-byte indices
+    # and records, then 2-byte window indices and records
+    want = 4 * (1 << 8) + 2 * 4 * (1 << 14) + (1 << 28) * (4 + 4 + 2 + 4)
     assert B.bs_staged_scratch_bytes((1 << 27) + 1, 4) == want
     assert B.bs_staged_scratch_bytes(0, 4) == 0
     assert B.bs_staged_scratch_bytes(1000, 3) == 0
@@ -385,3 +385,23 @@ def test_staged_table_lines(tmp_path):
     finally:
         B.bs_probe_set_staged_policy(2)
         assert B.bs_load_tuned_configs(B.TUNED_FILE) == B.BS_OK
+
+
+def test_int_rate_probe_argument_checks():
+    f = B.bs_probe_int_rate
+    assert f(0, 16, None, 8, None) == B.BS_EINVAL
+    assert f(6, 16, FAKE_OUT, 8, None) == B.BS_EINVAL
+    assert f(0, 0, FAKE_OUT, 8, None) == B.BS_EINVAL
+    assert f(0, (1 << 20) + 1, FAKE_OUT, 8, None) == B.BS_EINVAL
+    assert f(0, 16, FAKE_OUT, 0, None) == B.BS_EINVAL
+    assert f(0, 16, FAKE_OUT, 65537, None) == B.BS_EINVAL
+    assert f(0, 16, FAKE_OUT + 2, 8, None) == B.BS_EELEM
+
+
+def test_round_trip_probe_argument_checks():
+    f = B.bs_probe_round_trips
+    assert f(None, 32, 4, None) == B.BS_EINVAL
+    assert f(FAKE_OUT, 0, 4, None) == B.BS_EINVAL
+    assert f(FAKE_OUT, 65537, 4, None) == B.BS_EINVAL
+    assert f(FAKE_OUT, 32, 1025, None) == B.BS_EINVAL
+    assert f(FAKE_OUT + 2, 32, 4, None) == B.BS_EELEM
