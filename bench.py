@@ -120,6 +120,9 @@ def parse_args():
                         "and the u64 n = 2^27+1 shuffle, --steps each; no extras")
     p.add_argument("--profile", action="store_true",
                    help="profiler run: one copy of known size, then the steps; no extras")
+    p.add_argument("--profile-small", action="store_true",
+                   help="profiler run of the small workload (n = 100,000 uint32, 4 rounds): eager calls, graph "
+                        "replays, the launch floor and the round-trip probe; no extras")
     p.add_argument("--profile-batched", action="store_true",
                    help="profiler run of the batched workload: --steps batched launches, no extras")
     p.add_argument("--traffic-record", nargs="+", metavar="PATH",
@@ -735,6 +738,11 @@ def main() -> int:
     timer = Timer(torch, stream)
     rounds = args.rounds
 
+    if args.profile_small:
+        small = bench_small(torch, bs, dev, timer)
+        log(f"bench: small workload {json.dumps(small)}")
+        print(json.dumps({"small": small}), flush=True)
+        return 0
     if args.profile_batched:
         b = W.batch(4096, 100, 1_000_000, seed=3)
         total = b["total"]

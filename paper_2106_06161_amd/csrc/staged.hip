@@ -48,6 +48,15 @@ struct DistShape {
 };
 constexpr uint32_t kMaxFirstTile = 16384;
 
+// Waits for every vector memory operation this wavefront has issued
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).  Loads,
+// stores and atomics share one in-order counter, so a load consumed after
+// a loop of stores of unknown length makes the compiler wait for all of them:
+// waiting here, before the stores are issued, ends the loads' wait while
+// nothing else is in flight, and the stores then drain while the next work
+// proceeds.
+__device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Inclusive scan over the 64 lanes of a wavefront with DPP moves (no LDS
 // traffic, no lane-address registers): shifts by 1, 2, 4 and 8 within each
 // row of 16 lanes, then lane 15 of each row added into the next row and lane
@@ -226,6 +235,9 @@ __global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_first_ker
   uint32_t L[kItems], R[kItems], pos[kItems];
   uint32_t valid = load_tile<EB, S>(v, L, R, a, tile);
   vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+  // loads complete on both paths into the loop (see the wait before the
+  // stores), so staging never waits on the previous tile's stores
+  wait_vector_memory();
   for (;;) {
     for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
     __syncthreads();
@@ -245,6 +257,9 @@ __global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_first_ker
       vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
     }
     publish_bases<EB, S>(lds, res, digits);
+    // the next tile's loads (issued before its cipher) are in; the stores
+    // below then do not hold up the next tile's staging
+    wait_vector_memory();
     write_runs<EB, S>(lds, res.count, shift, digits, 0, cap, idx_out, windows, val_out);
     if (!more) break;
     tile = next;
@@ -309,20 +324,49 @@ __global__ __launch_bounds__(256) void staged_zero_kernel(const StagedArgs a) {
     for (uint32_t d = blockIdx.x * 256 + threadIdx.x; d < (1u << a.b1); d += gridDim.x * 256) a.cnt_a[d] = 0;
 }
 
-// Exclusive prefix of the window counts (one workgroup).
+// Exclusive prefix of the window counts (one workgroup).  Each thread owns
+// `per` consecutive windows (a power of two: the window count is one, and
+// with fewer windows than threads only the first threads own one); with
+// per >= 4 it moves them as 16-byte vectors.  The counts are read through a
+// restrict pointer so the second sweep's loads need not wait for the
+// first stores of the bases.
 __global__ __launch_bounds__(kScanThreads) void staged_scan_kernel(const StagedArgs a) {
   __shared__ uint32_t waves[kScanThreads / 64];
   const uint32_t windows = 1u << (a.b1 + a.b2);
   const uint32_t per = (windows + kScanThreads - 1) / kScanThreads;
   const uint32_t first = threadIdx.x * per;
-  uint32_t sum = 0;
-  for (uint32_t q = first; q < first + per && q < windows; ++q) sum += a.cnt_b[q];
+  const uint32_t* __restrict__ cnt = a.cnt_b;
+  uint32_t* __restrict__ base = a.base_b;
   uint32_t total;
-  uint32_t run = block_exclusive_scan<kScanThreads>(sum, waves, &total);
-  for (uint32_t q = first; q < first + per && q < windows; ++q) {
-    const uint32_t c = a.cnt_b[q];
-    a.base_b[q] = run;
-    run += c;
+  if (per >= 4) {
+    const u32x4* __restrict__ c4 = reinterpret_cast<const u32x4*>(cnt + first);
+    u32x4* __restrict__ b4 = reinterpret_cast<u32x4*>(base + first);
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per / 4; ++i) {
+      const u32x4 c = c4[i];
+      sum += c.x + c.y + c.z + c.w;
+    }
+    uint32_t run = block_exclusive_scan<kScanThreads>(sum, waves, &total);
+    for (uint32_t i = 0; i < per / 4; ++i) {
+      const u32x4 c = c4[i];
+      u32x4 b;
+      b.x = run;
+      b.y = run + c.x;
+      b.z = b.y + c.y;
+      b.w = b.z + c.z;
+      run = b.w + c.w;
+      b4[i] = b;
+    }
+  } else {
+    // per is 1 or 2; with fewer windows than threads the rest own none
+    const uint32_t mine = first < windows ? per : 0u;
+    uint32_t c[2] = {0u, 0u};
+    for (uint32_t i = 0; i < mine; ++i) c[i] = cnt[first + i];
+    uint32_t run = block_exclusive_scan<kScanThreads>(c[0] + c[1], waves, &total);
+    for (uint32_t i = 0; i < mine; ++i) {
+      base[first + i] = run;
+      run += c[i];
+    }
   }
 }
 
@@ -340,16 +384,24 @@ constexpr uint32_t kWindowBits = EB == 1 ? 16 : EB == 2 ? 15 : EB == 4 ? 14 : EB
 // one window.)
 constexpr uint32_t kPrefetch = 4;
 
+// kPrefetch entries per thread of a window, from entry e0 on: entry
+// e0 + j * T + tid (T threads), raw 16-bit slot and record.  The loads are
+// unconditional (no branch per load: a load under a lane mask leaves its
+// register pending for the compiler's wait counting, which then waits for
+// it, and everything older, at the register's next write).  The slot is masked where it is used, not here: an
+// operation on a loaded value right after its load would make the wavefront
+// wait for the load at that point.  The pointers are plain (not restrict):
+// loads through restrict pointers to data nothing writes may be moved past
+// the workgroup barriers, which would undo the prefetch.
 template <typename T>
-__device__ __forceinline__ void load_window_head(uint32_t (&il)[kPrefetch], T (&v)[kPrefetch],
-                                                 const StagedArgs& a, uint32_t q, uint32_t cnt, uint32_t wmask) {
-  const uint64_t first = uint64_t(q) << a.s;
+__device__ __forceinline__ void load_window_batch(uint32_t (&il)[kPrefetch], T (&v)[kPrefetch], const uint16_t* wi,
+                                                  const T* wv, uint32_t e0, uint32_t cnt) {
 #pragma unroll
   for (uint32_t j = 0; j < kPrefetch; ++j) {
-    const uint32_t e = threadIdx.x + j * kPlaceThreads;
-    const uint64_t g = first + (e < cnt ? e : 0u);
-    il[j] = a.idx_b[g] & wmask;
-    v[j] = reinterpret_cast<const T*>(a.val_b)[g];
+    const uint32_t e = e0 + j * kPlaceThreads + threadIdx.x;
+    const uint32_t ec = e < cnt ? e : 0u;  // lanes past the count re-read entry 0 (inside the window)
+    il[j] = wi[ec];
+    v[j] = wv[ec];
   }
 }
 
@@ -366,35 +418,58 @@ __global__ __launch_bounds__(kPlaceThreads, 8) void staged_place_kernel(const St
   __shared__ uint32_t waves[kPlaceThreads / 64];
   const uint32_t tid = threadIdx.x;
   const uint32_t windows = 1u << (a.b1 + a.b2);
+  // counts and bases are only read here: scalar loads, outside the vector
+  // memory counter that the record loads and output stores share
+  const ConstKeys cnts = global_keys(a.cnt_b);
+  const ConstKeys bases = global_keys(a.base_b);
   uint32_t q = blockIdx.x;
   if (q >= windows) return;
+  const uint16_t* wi = a.idx_b + (uint64_t(q) << a.s);
+  const T* wv = reinterpret_cast<const T*>(a.val_b) + (uint64_t(q) << a.s);
   uint32_t il[kPrefetch];
   T hv[kPrefetch];
-  uint32_t cnt = a.cnt_b[q];
-  load_window_head<T>(il, hv, a, q, cnt, W - 1);
+  uint32_t cnt = cnts[q];
+  uint32_t next_cnt = q + gridDim.x < windows ? cnts[q + gridDim.x] : 0u;
+  load_window_batch<T>(il, hv, wi, wv, 0, cnt);
+  wait_vector_memory();  // both paths into the loop arrive with the head loaded
   for (;;) {
-    const uint64_t base = a.base_b[q];
+    const uint32_t base = bases[q];
     for (uint32_t t = tid; t < W / 32; t += kPlaceThreads) bits[t] = 0;
     __syncthreads();
 #pragma unroll
     for (uint32_t j = 0; j < kPrefetch; ++j) {
       if (tid + j * kPlaceThreads < cnt) {
-        vals[il[j]] = hv[j];
-        atomicOr(&bits[il[j] >> 5], 1u << (il[j] & 31));
+        const uint32_t x = il[j] & (W - 1);
+        vals[x] = hv[j];
+        atomicOr(&bits[x >> 5], 1u << (x & 31));
       }
     }
-    const uint64_t first = uint64_t(q) << a.s;
-    for (uint32_t e = tid + kPrefetch * kPlaceThreads; e < cnt; e += kPlaceThreads) {
-      const uint32_t x = a.idx_b[first + e] & (W - 1);
-      vals[x] = reinterpret_cast<const T*>(a.val_b)[first + e];
-      atomicOr(&bits[x >> 5], 1u << (x & 31));
+    // the rest of the window, kPrefetch entries per thread per batch, each
+    // batch's loads issued together
+    for (uint32_t e0 = kPrefetch * kPlaceThreads; e0 < cnt; e0 += kPrefetch * kPlaceThreads) {
+      load_window_batch<T>(il, hv, wi, wv, e0, cnt);
+#pragma unroll
+      for (uint32_t j = 0; j < kPrefetch; ++j) {
+        if (e0 + j * kPlaceThreads + tid < cnt) {
+          const uint32_t x = il[j] & (W - 1);
+          vals[x] = hv[j];
+          atomicOr(&bits[x >> 5], 1u << (x & 31));
+        }
+      }
     }
     const uint32_t cur_cnt = cnt;
     const uint32_t next = q + gridDim.x;
     const bool more = next < windows;
     if (more) {
-      cnt = a.cnt_b[next];
-      load_window_head<T>(il, hv, a, next, cnt, W - 1);
+      // the next window's head goes out now and lands during the ranking
+      cnt = next_cnt;
+      next_cnt = next + gridDim.x < windows ? cnts[next + gridDim.x] : 0u;
+      wi = a.idx_b + (uint64_t(next) << a.s);
+      wv = reinterpret_cast<const T*>(a.val_b) + (uint64_t(next) << a.s);
+      load_window_batch<T>(il, hv, wi, wv, 0, cnt);
+      // keeps the compiler from sinking these loads to their use in the
+      // next iteration (after the output stores)
+      asm volatile("" ::: "memory");
     }
     __syncthreads();
     const uint32_t slot0 = tid * kPer;
@@ -417,7 +492,10 @@ __global__ __launch_bounds__(kPlaceThreads, 8) void staged_place_kernel(const St
       if ((mine >> j) & 1u) vals[start + uint32_t(__builtin_popcountll(below))] = r[j];
     }
     __syncthreads();
-    for (uint32_t t = tid; t < cur_cnt; t += kPlaceThreads) reinterpret_cast<T*>(a.out)[base + t] = vals[t];
+    // the next window's head loads are in before the output stores go out
+    wait_vector_memory();
+    T* __restrict__ wo = reinterpret_cast<T*>(a.out) + base;
+    for (uint32_t t = tid; t < cur_cnt; t += kPlaceThreads) wo[t] = vals[t];
     __syncthreads();
     if (!more) break;
     q = next;
