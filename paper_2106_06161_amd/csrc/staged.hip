@@ -117,7 +117,8 @@ struct DistLds {
 //                   bits of i: the place pass needs i mod 2^s, s <= 16.
 template <typename S>
 struct Reservation {
-  uint32_t h[S::kDigitsPerThread];  // this thread's digits: entries in the tile
+  uint32_t h[S::kDigitsPerThread];  // this thread's digits: entries in the tile,
+  uint32_t s[S::kDigitsPerThread];  // their first position in the tile
   uint32_t g[S::kDigitsPerThread];  // and the reserved position in their bucket
   uint32_t count;                   // entries in the tile
 };
@@ -138,6 +139,7 @@ __device__ __forceinline__ void reserve_runs(DistLds<EB, S>& lds, Reservation<S>
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j) {
     const uint32_t d = tid * kPer + j;
+    r.s[j] = run;
     if (d < digits) {
       lds.start[d] = run;
       r.g[j] = r.h[j] ? atomicAdd(&counts[bucket_first + d], r.h[j]) : 0u;
@@ -163,30 +165,55 @@ __device__ __forceinline__ void stage_entries(DistLds<EB, S>& lds, const uint32_
   }
 }
 
+// gbase[d] = the bucket-array entry of the tile's position 0 in digit d's
+// run: (first bucket + d) * capacity + reserved position - start of the run
+// in the tile, mod 2^32 (every bucket-array entry index is below 2^32: the
+// domain is at most 2^32), so an entry's destination is gbase[d] + position.
 template <int EB, typename S>
-__device__ __forceinline__ void publish_bases(DistLds<EB, S>& lds, const Reservation<S>& r, uint32_t digits) {
+__device__ __forceinline__ void publish_bases(DistLds<EB, S>& lds, const Reservation<S>& r, uint32_t digits,
+                                              uint32_t bucket_first, uint32_t cap) {
   constexpr uint32_t kPer = S::kDigitsPerThread;
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j) {
     const uint32_t d = threadIdx.x * kPer + j;
-    if (d < digits && r.h[j]) lds.gbase[d] = r.g[j];
+    if (d < digits && r.h[j]) lds.gbase[d] = (bucket_first + d) * cap + r.g[j] - r.s[j];
   }
   __syncthreads();
 }
 
-template <int EB, typename S>
+// Each run to its bucket: thread t writes tile positions t, t + T, ... (T
+// threads), four at a time: the LDS reads of a group first (positions past
+// the count re-read position 0), then the destinations, then the stores under
+// the count.  WIN: windows keep only the low 16 bits of i.
+template <int EB, typename S, bool WIN>
 __device__ __forceinline__ void write_runs(DistLds<EB, S>& lds, uint32_t count, uint32_t shift, uint32_t digits,
-                                           uint64_t bucket_first, uint64_t cap, void* __restrict__ idx_out,
-                                           bool windows, uint8_t* __restrict__ val_out) {
-  for (uint32_t p = threadIdx.x; p < count; p += S::kThreads) {
-    const uint32_t ii = lds.idx[p];
-    const uint32_t d = (ii >> shift) & (digits - 1);
-    const uint64_t g = (bucket_first + d) * cap + lds.gbase[d] + (p - lds.start[d]);
-    if (windows)
-      static_cast<uint16_t*>(idx_out)[g] = uint16_t(ii);
-    else
-      static_cast<uint32_t*>(idx_out)[g] = ii;
-    store_record<EB, false>(val_out, g, lds.val[p]);
+                                           void* __restrict__ idx_out, uint8_t* __restrict__ val_out) {
+  using T = typename Payload<EB>::T;
+  constexpr uint32_t kGroup = S::kItems < 4 ? S::kItems : 4;
+#pragma unroll 1
+  for (uint32_t j0 = 0; j0 < S::kItems; j0 += kGroup) {
+    uint32_t ii[kGroup], g[kGroup];
+    T v[kGroup];
+#pragma unroll
+    for (uint32_t j = 0; j < kGroup; ++j) {
+      const uint32_t p = (j0 + j) * S::kThreads + threadIdx.x;
+      const uint32_t pc = p < count ? p : 0u;
+      ii[j] = lds.idx[pc];
+      v[j] = lds.val[pc];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kGroup; ++j)
+      g[j] = lds.gbase[(ii[j] >> shift) & (digits - 1)] + (j0 + j) * S::kThreads + threadIdx.x;
+#pragma unroll
+    for (uint32_t j = 0; j < kGroup; ++j) {
+      if ((j0 + j) * S::kThreads + threadIdx.x < count) {
+        if constexpr (WIN)
+          static_cast<uint16_t*>(idx_out)[g[j]] = uint16_t(ii[j]);
+        else
+          static_cast<uint32_t*>(idx_out)[g[j]] = ii[j];
+        store_record<EB, false>(val_out, g[j], v[j]);
+      }
+    }
   }
   __syncthreads();
 }
@@ -256,11 +283,14 @@ __global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_first_ker
       valid = load_tile<EB, S>(v, L, R, a, next);
       vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
     }
-    publish_bases<EB, S>(lds, res, digits);
+    publish_bases<EB, S>(lds, res, digits, 0u, uint32_t(cap));
     // the next tile's loads (issued before its cipher) are in; the stores
     // below then do not hold up the next tile's staging
     wait_vector_memory();
-    write_runs<EB, S>(lds, res.count, shift, digits, 0, cap, idx_out, windows, val_out);
+    if (windows)
+      write_runs<EB, S, true>(lds, res.count, shift, digits, idx_out, val_out);
+    else
+      write_runs<EB, S, false>(lds, res.count, shift, digits, idx_out, val_out);
     if (!more) break;
     tile = next;
   }
@@ -311,8 +341,8 @@ __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_ke
     Reservation<S> res;
     reserve_runs<EB, S>(lds, res, digits, d1 << a.b2, a.cnt_b);
     stage_entries<EB, S>(lds, ii, v, pos, valid, a.s, digits);
-    publish_bases<EB, S>(lds, res, digits);
-    write_runs<EB, S>(lds, res.count, a.s, digits, d1 << a.b2, cap_b, a.idx_b, true, a.val_b);
+    publish_bases<EB, S>(lds, res, digits, uint32_t(d1 << a.b2), uint32_t(cap_b));
+    write_runs<EB, S, true>(lds, res.count, a.s, digits, a.idx_b, a.val_b);
   }
 }
 
