@@ -226,17 +226,23 @@ __device__ __forceinline__ void write_runs(DistLds<EB, S>& lds, uint32_t count, 
 template <int EB, typename S>
 __device__ __forceinline__ uint32_t load_tile(typename Payload<EB>::T (&v)[S::kItems], uint32_t (&L)[S::kItems],
                                               uint32_t (&R)[S::kItems], const StagedArgs& a, uint64_t tile) {
+  // 32-bit lane arithmetic: the staged form's domain is at most 2^32, so
+  // every y fits; the tile's first record and its remaining count are uniform
   const uint64_t y0 = tile * S::kTile;
+  const uint64_t left64 = a.n - y0;
+  const uint32_t left = left64 < S::kTile ? uint32_t(left64) : S::kTile;  // >= 1
+  const uint8_t* base = a.in + y0 * EB;
   uint32_t valid = 0;
 #pragma unroll
   for (uint32_t j = 0; j < S::kItems; ++j) {
-    const uint64_t y = y0 + j * S::kThreads + threadIdx.x;
-    const bool ok = y < a.n;
-    const uint64_t yc = ok ? y : a.n - 1;  // idle lanes re-read the last record and keep nothing
+    const uint32_t off = j * S::kThreads + threadIdx.x;
+    const bool ok = off < left;
+    const uint32_t oc = ok ? off : left - 1;  // idle lanes re-read the tile's last record and keep nothing
     valid |= ok ? (1u << j) : 0u;
-    v[j] = load_record<EB>(a.in, yc);
-    L[j] = uint32_t(yc >> a.cs.r) & a.cs.wmask;
-    R[j] = uint32_t(yc) & a.cs.rmask;
+    v[j] = load_record<EB>(base + oc * uint32_t(EB), 0);  // uniform base + 32-bit lane offset
+    const uint32_t y = uint32_t(y0) + oc;
+    L[j] = (y >> a.cs.r) & a.cs.wmask;
+    R[j] = y & a.cs.rmask;
   }
   return valid;
 }
