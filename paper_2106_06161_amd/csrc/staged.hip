@@ -32,19 +32,29 @@ constexpr uint32_t kMaxDigits = 1u << kMaxDigitBits;
 constexpr uint32_t kPlaceThreads = 1024;
 constexpr uint32_t kScanThreads = 1024;
 
-// Tile shapes of the two distribution passes.  The first pass takes as many
-// records per tile as its LDS staging area holds with one workgroup per CU:
-// every record of a tile that lands in the same bucket shares one global
-// reservation, and all tiles reserve from the same 2^b1 counters, so large
-// tiles keep those few counters from serializing the pass.  The second pass
-// spreads its reservations over 2^(b1 + b2) window counters and uses 4,096-
-// record tiles with several workgroups per CU.
+// Tile shapes of the distribution passes (PASS 1: first pass, PASS 3: first
+// pass with two workgroups per CU, PASS 2: second pass).  The first pass takes
+// as many records per tile as its LDS staging area holds with one workgroup
+// per CU: every record of a tile that lands in the same bucket shares one
+// global reservation, and all tiles reserve from the same 2^b1 counters, so
+// large tiles keep those few counters from serializing the pass.  Its other
+// shape (PASS 3: 8,192-record tiles on 512 threads) runs two workgroups per
+// CU, whose phases overlap the cipher with the other's memory work; it pays
+// off for odd k, whose inverse round costs eight instructions instead of
+// five, as long as 2^b1 <= 256 keeps its runs at 32 records or more.  The
+// second pass spreads its reservations over 2^(b1 + b2) window counters and
+// uses 8,192-record tiles with two workgroups per CU.
 template <int EB, int PASS>
 struct DistShape {
-  static constexpr uint32_t kThreads = PASS == 1 ? 1024u : (EB <= 8 ? 512u : 1024u);
-  static constexpr uint32_t kTile = PASS == 1 ? (EB <= 4 ? 16384u : EB == 8 ? 8192u : 4096u) : (EB <= 4 ? 8192u : 4096u);
+  static constexpr uint32_t kThreads =
+      PASS == 1 ? 1024u : PASS == 3 ? (EB <= 4 ? 512u : 1024u) : (EB <= 8 ? 512u : 1024u);
+  static constexpr uint32_t kTile = PASS != 2 ? (PASS == 3 && EB <= 4 ? 8192u : EB <= 4 ? 16384u : EB == 8 ? 8192u : 4096u)
+                                              : (EB <= 4 ? 8192u : 4096u);
   static constexpr uint32_t kItems = kTile / kThreads;
   static constexpr uint32_t kDigitsPerThread = (kMaxDigits + kThreads - 1) / kThreads;
+  // wavefronts per SIMD the register budget must allow (two workgroups per CU
+  // for the PASS 3 shape, one otherwise)
+  static constexpr uint32_t kMinWavesPerEU = PASS == 3 && EB <= 4 ? 2u * kThreads / 256u : kThreads / 256u;
 };
 constexpr uint32_t kMaxFirstTile = 16384;
 
@@ -247,9 +257,10 @@ __device__ __forceinline__ uint32_t load_tile(typename Payload<EB>::T (&v)[S::kI
   return valid;
 }
 
-template <int EB, bool ODD>
-__global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_first_kernel(const StagedArgs a) {
-  using S = DistShape<EB, 1>;
+template <int EB, bool ODD, bool SMALL>
+__global__ __launch_bounds__((DistShape<EB, SMALL ? 3 : 1>::kThreads), (DistShape<EB, SMALL ? 3 : 1>::kMinWavesPerEU))
+void staged_first_kernel(const StagedArgs a) {
+  using S = DistShape<EB, SMALL ? 3 : 1>;
   using T = typename Payload<EB>::T;
   constexpr uint32_t kItems = S::kItems;
   __shared__ DistLds<EB, S> lds;
@@ -546,22 +557,32 @@ uint32_t resident_groups(const void* fn, uint32_t threads, uint32_t num_cus) {
   return uint32_t(per_cu) * (num_cus ? num_cus : 1);
 }
 
+// First pass: persistent, as many workgroups as stay resident.
+template <int EB, bool ODD, bool SMALL>
+void launch_first(const StagedArgs& a, uint32_t num_cus, hipStream_t stream) {
+  using S1 = DistShape<EB, SMALL ? 3 : 1>;
+  const uint64_t tiles = (a.n + S1::kTile - 1) / S1::kTile;
+  const uint64_t r1 =
+      resident_groups(reinterpret_cast<const void*>(&staged_first_kernel<EB, ODD, SMALL>), S1::kThreads, num_cus);
+  const dim3 g1(uint32_t(tiles < r1 ? tiles : r1));
+  hipLaunchKernelGGL((staged_first_kernel<EB, ODD, SMALL>), g1, dim3(S1::kThreads), 0, stream, a);
+}
+
 template <int EB>
 hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hipStream_t stream) {
-  using S1 = DistShape<EB, 1>;
   using S2 = DistShape<EB, 2>;
   const uint32_t zero_groups = std::max(1u, std::min(256u, (1u << (a.b1 + a.b2)) / 256u));
   hipLaunchKernelGGL(staged_zero_kernel, dim3(zero_groups), dim3(256), 0, stream, a);
-  // first pass: persistent, as many workgroups as stay resident
-  const uint64_t tiles = (a.n + S1::kTile - 1) / S1::kTile;
-  const void* first = odd ? reinterpret_cast<const void*>(&staged_first_kernel<EB, true>)
-                          : reinterpret_cast<const void*>(&staged_first_kernel<EB, false>);
-  const uint64_t r1 = resident_groups(first, S1::kThreads, num_cus);
-  const dim3 g1(uint32_t(tiles < r1 ? tiles : r1));
-  if (odd)
-    hipLaunchKernelGGL((staged_first_kernel<EB, true>), g1, dim3(S1::kThreads), 0, stream, a);
-  else
-    hipLaunchKernelGGL((staged_first_kernel<EB, false>), g1, dim3(S1::kThreads), 0, stream, a);
+  if (!odd)
+    launch_first<EB, false, false>(a, num_cus, stream);
+  else if constexpr (EB <= 4) {
+    if (a.b1 <= 8)
+      launch_first<EB, true, true>(a, num_cus, stream);
+    else
+      launch_first<EB, true, false>(a, num_cus, stream);
+  } else {
+    launch_first<EB, true, false>(a, num_cus, stream);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.b2) {
