@@ -341,14 +341,19 @@ __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_ke
     T v[kItems];
     uint32_t ii[kItems], pos[kItems];
     uint32_t valid = 0;
+    // the tile's entries from a uniform base and 32-bit lane offsets
+    const uint64_t g0 = d1 * cap_a + first;
+    const uint32_t* __restrict__ ti = a.idx_a + g0;
+    const uint8_t* tv = a.val_a + g0 * EB;
+    const uint32_t left = cnt - uint32_t(first);  // >= 1
 #pragma unroll
     for (uint32_t j = 0; j < kItems; ++j) {
-      const uint64_t e = first + j * S::kThreads + tid;
-      const bool ok = e < cnt;
+      const uint32_t off = j * S::kThreads + tid;
+      const bool ok = off < left;
       valid |= ok ? (1u << j) : 0u;
-      const uint64_t g = d1 * cap_a + (ok ? e : first);
-      ii[j] = a.idx_a[g];
-      v[j] = load_record<EB>(a.val_a, g);
+      const uint32_t oc = ok ? off : 0u;  // idle lanes re-read the tile's first entry
+      ii[j] = ti[oc];
+      v[j] = load_record<EB>(tv + oc * uint32_t(EB), 0);
     }
     __syncthreads();  // the histogram is cleared
 #pragma unroll
