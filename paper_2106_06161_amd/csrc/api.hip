@@ -249,6 +249,9 @@ StagedLayout staged_layout(uint64_t n, uint32_t elem_bytes) {
   l.cnt_b = l.cnt_a + align256((uint64_t(1) << l.b1) * 4);
   l.base_b = l.cnt_b + align256(windows * 4);
   l.idx_a = l.base_b + align256(windows * 4);
+  // domain * 4 is a multiple of 256 here (k >= 14 whenever b2 > 0), so the
+  // value part follows the index part with no gap: 4-byte records keep their
+  // first-pass entries as (index, record) pairs over both parts
   l.val_a = l.idx_a + (l.b2 ? align256(domain * 4) : 0);
   l.idx_b = l.val_a + (l.b2 ? align256(domain * elem_bytes) : 0);
   l.val_b = l.idx_b + align256(domain * 2);

@@ -118,7 +118,7 @@ struct StagedArgs {
   uint32_t rounds;
   uint32_t s;       // window bits
   uint32_t b1, b2;  // digit bits of the first and second distribution passes (b2 = 0: one pass)
-  uint32_t* idx_a;
+  uint32_t* idx_a;   // bucket entries' padded indices (4-byte records: (index, record) pairs over idx_a and val_a)
   uint8_t* val_a;
   uint32_t* cnt_a;   // 2^b1 bucket counts
   uint16_t* idx_b;   // low 16 bits of the padded index (the place pass needs i mod 2^s, s <= 16)

@@ -40,8 +40,10 @@ constexpr uint32_t kScanThreads = 1024;
 // large tiles keep those few counters from serializing the pass.  Its other
 // shape (PASS 3: 8,192-record tiles on 512 threads) runs two workgroups per
 // CU, whose phases overlap the cipher with the other's memory work; it pays
-// off for odd k, whose inverse round costs eight instructions instead of
-// five, as long as 2^b1 <= 256 keeps its runs at 32 records or more.  The
+// off once the inverse cipher is long (a round costs five instructions for
+// even k, eight for odd k), as long as 2^b1 <= 256 keeps its runs at 32
+// records or more; with a short cipher the larger tiles' fewer reservations
+// win.  The
 // second pass spreads its reservations over 2^(b1 + b2) window counters and
 // uses 8,192-record tiles with two workgroups per CU.
 template <int EB, int PASS>
@@ -57,6 +59,13 @@ struct DistShape {
   static constexpr uint32_t kMinWavesPerEU = PASS == 3 && EB <= 4 ? 2u * kThreads / 256u : kThreads / 256u;
 };
 constexpr uint32_t kMaxFirstTile = 16384;
+
+// Two-pass bucket entries of 4-byte records are written as one 8-byte pair
+// (padded index, record) at idx_a[2 e] (the index and record arrays are
+// adjacent in the scratch): one store per entry in the first pass and one
+// load in the second, instead of two each.
+template <int EB>
+constexpr bool kPairedBuckets = EB == 4;
 
 // Waits for every vector memory operation this wavefront has issued
 // (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).  Loads,
@@ -108,8 +117,12 @@ struct DistLds {
   uint32_t start[kMaxDigits];
   uint32_t gbase[kMaxDigits];
   uint32_t waves[S::kThreads / 64];
-  uint32_t idx[S::kTile];
-  typename Payload<EB>::T val[S::kTile];
+  // the tile's entries in digit order: (index, record) pairs for 4-byte
+  // records (one 8-byte LDS access each), separate arrays otherwise
+  static constexpr bool kPaired = EB == 4;
+  u32x2 pair[kPaired ? S::kTile : 1];
+  uint32_t idx[kPaired ? 1 : S::kTile];
+  typename Payload<EB>::T val[kPaired ? 1 : S::kTile];
 };
 
 // One distribution tile of (i, record) entries, sorted by digit
@@ -169,8 +182,12 @@ __device__ __forceinline__ void stage_entries(DistLds<EB, S>& lds, const uint32_
     if ((valid >> j) & 1u) {
       const uint32_t d = (i[j] >> shift) & (digits - 1);
       const uint32_t p = lds.start[d] + pos[j];
-      lds.idx[p] = i[j];
-      lds.val[p] = v[j];
+      if constexpr (DistLds<EB, S>::kPaired) {
+        lds.pair[p] = u32x2{i[j], v[j]};
+      } else {
+        lds.idx[p] = i[j];
+        lds.val[p] = v[j];
+      }
     }
   }
 }
@@ -208,8 +225,14 @@ __device__ __forceinline__ void write_runs(DistLds<EB, S>& lds, uint32_t count, 
     for (uint32_t j = 0; j < kGroup; ++j) {
       const uint32_t p = (j0 + j) * S::kThreads + threadIdx.x;
       const uint32_t pc = p < count ? p : 0u;
-      ii[j] = lds.idx[pc];
-      v[j] = lds.val[pc];
+      if constexpr (DistLds<EB, S>::kPaired) {
+        const u32x2 e = lds.pair[pc];
+        ii[j] = e.x;
+        v[j] = e.y;
+      } else {
+        ii[j] = lds.idx[pc];
+        v[j] = lds.val[pc];
+      }
     }
 #pragma unroll
     for (uint32_t j = 0; j < kGroup; ++j)
@@ -217,11 +240,15 @@ __device__ __forceinline__ void write_runs(DistLds<EB, S>& lds, uint32_t count, 
 #pragma unroll
     for (uint32_t j = 0; j < kGroup; ++j) {
       if ((j0 + j) * S::kThreads + threadIdx.x < count) {
-        if constexpr (WIN)
+        if constexpr (WIN) {
           static_cast<uint16_t*>(idx_out)[g[j]] = uint16_t(ii[j]);
-        else
+          store_record<EB, false>(val_out, g[j], v[j]);
+        } else if constexpr (kPairedBuckets<EB>) {
+          static_cast<u32x2*>(idx_out)[g[j]] = u32x2{ii[j], v[j]};
+        } else {
           static_cast<uint32_t*>(idx_out)[g[j]] = ii[j];
-        store_record<EB, false>(val_out, g[j], v[j]);
+          store_record<EB, false>(val_out, g[j], v[j]);
+        }
       }
     }
   }
@@ -345,6 +372,7 @@ __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_ke
     const uint64_t g0 = d1 * cap_a + first;
     const uint32_t* __restrict__ ti = a.idx_a + g0;
     const uint8_t* tv = a.val_a + g0 * EB;
+    const u32x2* __restrict__ tp = reinterpret_cast<const u32x2*>(a.idx_a) + g0;
     const uint32_t left = cnt - uint32_t(first);  // >= 1
 #pragma unroll
     for (uint32_t j = 0; j < kItems; ++j) {
@@ -352,8 +380,14 @@ __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_ke
       const bool ok = off < left;
       valid |= ok ? (1u << j) : 0u;
       const uint32_t oc = ok ? off : 0u;  // idle lanes re-read the tile's first entry
-      ii[j] = ti[oc];
-      v[j] = load_record<EB>(tv + oc * uint32_t(EB), 0);
+      if constexpr (kPairedBuckets<EB>) {
+        const u32x2 r = tp[oc];
+        ii[j] = r.x;
+        v[j] = r.y;
+      } else {
+        ii[j] = ti[oc];
+        v[j] = load_record<EB>(tv + oc * uint32_t(EB), 0);
+      }
     }
     __syncthreads();  // the histogram is cleared
 #pragma unroll
@@ -578,10 +612,21 @@ hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hip
   using S2 = DistShape<EB, 2>;
   const uint32_t zero_groups = std::max(1u, std::min(256u, (1u << (a.b1 + a.b2)) / 256u));
   hipLaunchKernelGGL(staged_zero_kernel, dim3(zero_groups), dim3(256), 0, stream, a);
-  if (!odd)
-    launch_first<EB, false, false>(a, num_cus, stream);
-  else if constexpr (EB <= 4) {
-    if (a.b1 <= 8)
+  // the two-workgroups-per-CU first pass once the inverse cipher is long
+  // enough for overlap to pay (about 80 instructions: five per even-k round,
+  // eight per odd-k round) and 2^b1 <= 256 keeps its runs long
+  const bool small_ok = a.b1 <= 8 && a.rounds * (odd ? 8u : 5u) >= 80u;
+  if (!odd) {
+    if constexpr (EB <= 4) {
+      if (small_ok)
+        launch_first<EB, false, true>(a, num_cus, stream);
+      else
+        launch_first<EB, false, false>(a, num_cus, stream);
+    } else {
+      launch_first<EB, false, false>(a, num_cus, stream);
+    }
+  } else if constexpr (EB <= 4) {
+    if (small_ok)
       launch_first<EB, true, true>(a, num_cus, stream);
     else
       launch_first<EB, true, false>(a, num_cus, stream);

@@ -44,9 +44,9 @@ def staged(x_np, seed, rounds):
 
 
 # (n, elem_bytes): single window (k <= s), one pass, the widest one-pass split,
-# two passes; odd and even k (odd k with 2^b1 <= 256 and records of at most 4
-# bytes takes the first pass's two-workgroups-per-CU shape, one pass or two);
-# ragged tails
+# two passes; odd and even k (at 24 rounds, records of at most 4 bytes with
+# 2^b1 <= 256 take the first pass's two-workgroups-per-CU shape, one pass or
+# two); ragged tails
 CASES = [(1, 4), (5, 4), (1000, 4), (4097, 4), (100_000, 4), ((1 << 20) + 1, 4), ((1 << 22) + 3, 4),
          ((1 << 23) + 1, 4), ((1 << 24) - 5, 4), ((1 << 24) + 1, 4), (70_001, 1), ((1 << 22) + 1, 1),
          (100_003, 2), ((1 << 23) + 7, 2), ((1 << 24) + 3, 2), (65_537, 8), ((1 << 21) + 1, 8),
@@ -63,6 +63,19 @@ def test_staged_equals_oracle(n, eb):
 def test_staged_round_counts(rounds):
     x = records((1 << 23) + 1, 4, seed=3)
     assert np.array_equal(staged(x, 9, rounds), oracle.shuffle(x, 9, rounds))
+
+
+# The first pass takes its two-workgroups-per-CU shape once the inverse cipher
+# is long (rounds x 5 instructions for even k, x 8 for odd k, at least 80) and
+# the larger one-workgroup shape below that: both sides of the switch, both
+# parities of k, 4-, 2- and 1-byte records.
+@pytest.mark.parametrize("n,eb,rounds", [((1 << 23) + 1, 4, 15), ((1 << 23) + 1, 4, 16), ((1 << 24) + 1, 4, 9),
+                                         ((1 << 24) + 1, 4, 10), ((1 << 21) + 5, 2, 15), ((1 << 21) + 5, 2, 16),
+                                         ((1 << 24) + 3, 2, 9), ((1 << 23) + 1, 1, 15), ((1 << 23) + 1, 1, 16),
+                                         ((1 << 22) + 1, 1, 10)])
+def test_staged_first_pass_shapes(n, eb, rounds):
+    x = records(n, eb, seed=rounds)
+    assert np.array_equal(staged(x, 77, rounds), oracle.shuffle(x, 77, rounds)), (n, eb, rounds)
 
 
 def test_staged_splits():
