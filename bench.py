@@ -57,7 +57,7 @@ KERNEL_SOURCES = [
     "paper_2106_06161_amd/csrc/staged.hip",
 ]
 STAGED_KERNELS = ["bsd::(anonymous namespace)::staged_zero_kernel(bsd::StagedArgs)",
-                  "void bsd::(anonymous namespace)::staged_first_kernel<4, false>(bsd::StagedArgs)",
+                  "void bsd::(anonymous namespace)::staged_first_kernel<4, false, true>(bsd::StagedArgs)",
                   "void bsd::(anonymous namespace)::staged_second_kernel<4>(bsd::StagedArgs)",
                   "bsd::(anonymous namespace)::staged_scan_kernel(bsd::StagedArgs)",
                   "void bsd::(anonymous namespace)::staged_place_kernel<4>(bsd::StagedArgs)"]

@@ -60,6 +60,32 @@ struct DistShape {
 };
 constexpr uint32_t kMaxFirstTile = 16384;
 
+// Buffer resource word 3 for raw (unformatted, unswizzled) 32-bit-format
+// buffer accesses on gfx9-family chips.
+constexpr int kBufferWord3 = 0x00020000;
+
+template <int EB>
+__device__ __forceinline__ typename Payload<EB>::T buffer_load_record(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                                      uint32_t soff) {
+  if constexpr (EB == 1) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
+  } else if constexpr (EB == 2) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+  } else if constexpr (EB == 4) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  } else if constexpr (EB == 8) {
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return uint64_t(w[0]) | (uint64_t(w[1]) << 32);
+  } else {
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return Rec16{uint64_t(w[0]) | (uint64_t(w[1]) << 32), uint64_t(w[2]) | (uint64_t(w[3]) << 32)};
+  }
+}
+
+// The valid-item mask of a whole tile.
+template <typename S>
+constexpr uint32_t kAllItems = S::kItems >= 32 ? ~0u : (1u << S::kItems) - 1u;
+
 // Two-pass bucket entries of 4-byte records are written as one 8-byte pair
 // (padded index, record) at idx_a[2 e] (the index and record arrays are
 // adjacent in the scratch): one store per entry in the first pass and one
@@ -177,18 +203,23 @@ __device__ __forceinline__ void stage_entries(DistLds<EB, S>& lds, const uint32_
                                               const typename Payload<EB>::T (&v)[S::kItems],
                                               const uint32_t (&pos)[S::kItems], uint32_t valid, uint32_t shift,
                                               uint32_t digits) {
-#pragma unroll
-  for (uint32_t j = 0; j < S::kItems; ++j) {
-    if ((valid >> j) & 1u) {
-      const uint32_t d = (i[j] >> shift) & (digits - 1);
-      const uint32_t p = lds.start[d] + pos[j];
-      if constexpr (DistLds<EB, S>::kPaired) {
-        lds.pair[p] = u32x2{i[j], v[j]};
-      } else {
-        lds.idx[p] = i[j];
-        lds.val[p] = v[j];
-      }
+  const uint32_t dbits = __builtin_ctz(digits);
+  auto put = [&](uint32_t j) {
+    const uint32_t p = lds.start[__builtin_amdgcn_ubfe(i[j], shift, dbits)] + pos[j];
+    if constexpr (DistLds<EB, S>::kPaired) {
+      lds.pair[p] = u32x2{i[j], v[j]};
+    } else {
+      lds.idx[p] = i[j];
+      lds.val[p] = v[j];
     }
+  };
+  if (valid == kAllItems<S>) {  // a whole tile: no per-item checks
+#pragma unroll
+    for (uint32_t j = 0; j < S::kItems; ++j) put(j);
+  } else {
+#pragma unroll
+    for (uint32_t j = 0; j < S::kItems; ++j)
+      if ((valid >> j) & 1u) put(j);
   }
 }
 
@@ -217,6 +248,45 @@ __device__ __forceinline__ void write_runs(DistLds<EB, S>& lds, uint32_t count, 
                                            void* __restrict__ idx_out, uint8_t* __restrict__ val_out) {
   using T = typename Payload<EB>::T;
   constexpr uint32_t kGroup = S::kItems < 4 ? S::kItems : 4;
+  if (count == S::kTile) {
+    // a whole tile: no position checks, LDS reads at fixed offsets from the
+    // group's first position
+    const uint32_t dbits = __builtin_ctz(digits);
+#pragma unroll 1
+    for (uint32_t j0 = 0; j0 < S::kItems; j0 += kGroup) {
+      const uint32_t p0 = j0 * S::kThreads + threadIdx.x;
+      uint32_t ii[kGroup], g[kGroup];
+      T v[kGroup];
+#pragma unroll
+      for (uint32_t j = 0; j < kGroup; ++j) {
+        if constexpr (DistLds<EB, S>::kPaired) {
+          const u32x2 e = lds.pair[p0 + j * S::kThreads];
+          ii[j] = e.x;
+          v[j] = e.y;
+        } else {
+          ii[j] = lds.idx[p0 + j * S::kThreads];
+          v[j] = lds.val[p0 + j * S::kThreads];
+        }
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kGroup; ++j)
+        g[j] = lds.gbase[__builtin_amdgcn_ubfe(ii[j], shift, dbits)] + p0 + j * S::kThreads;
+#pragma unroll
+      for (uint32_t j = 0; j < kGroup; ++j) {
+        if constexpr (WIN) {
+          static_cast<uint16_t*>(idx_out)[g[j]] = uint16_t(ii[j]);
+          store_record<EB, false>(val_out, g[j], v[j]);
+        } else if constexpr (kPairedBuckets<EB>) {
+          static_cast<u32x2*>(idx_out)[g[j]] = u32x2{ii[j], v[j]};
+        } else {
+          static_cast<uint32_t*>(idx_out)[g[j]] = ii[j];
+          store_record<EB, false>(val_out, g[j], v[j]);
+        }
+      }
+    }
+    __syncthreads();
+    return;
+  }
 #pragma unroll 1
   for (uint32_t j0 = 0; j0 < S::kItems; j0 += kGroup) {
     uint32_t ii[kGroup], g[kGroup];
@@ -269,6 +339,21 @@ __device__ __forceinline__ uint32_t load_tile(typename Payload<EB>::T (&v)[S::kI
   const uint64_t left64 = a.n - y0;
   const uint32_t left = left64 < S::kTile ? uint32_t(left64) : S::kTile;  // >= 1
   const uint8_t* base = a.in + y0 * EB;
+  if (left == S::kTile) {
+    // a whole tile: buffer loads over the tile's bytes, the same lane offset
+    // for every item and the item's offset in a scalar register (every
+    // access inside the tile)
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), 0, int(S::kTile * EB), kBufferWord3);
+#pragma unroll
+    for (uint32_t j = 0; j < S::kItems; ++j) {
+      v[j] = buffer_load_record<EB>(rsrc, threadIdx.x * EB, j * S::kThreads * EB);
+      const uint32_t y = uint32_t(y0) + j * S::kThreads + threadIdx.x;
+      L[j] = __builtin_amdgcn_ubfe(y, a.cs.r, a.cs.w);
+      R[j] = y & a.cs.rmask;
+    }
+    return kAllItems<S>;
+  }
   uint32_t valid = 0;
 #pragma unroll
   for (uint32_t j = 0; j < S::kItems; ++j) {
@@ -278,7 +363,7 @@ __device__ __forceinline__ uint32_t load_tile(typename Payload<EB>::T (&v)[S::kI
     valid |= ok ? (1u << j) : 0u;
     v[j] = load_record<EB>(base + oc * uint32_t(EB), 0);  // uniform base + 32-bit lane offset
     const uint32_t y = uint32_t(y0) + oc;
-    L[j] = (y >> a.cs.r) & a.cs.wmask;
+    L[j] = __builtin_amdgcn_ubfe(y, a.cs.r, a.cs.w);
     R[j] = y & a.cs.rmask;
   }
   return valid;
@@ -313,9 +398,14 @@ void staged_first_kernel(const StagedArgs a) {
     for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
     __syncthreads();
 #pragma unroll
-    for (uint32_t j = 0; j < kItems; ++j) {
-      L[j] = (L[j] << a.cs.r) | R[j];  // the padded index i whose image is y
-      pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[L[j] >> shift], 1u) : 0u;
+    for (uint32_t j = 0; j < kItems; ++j) L[j] = (L[j] << a.cs.r) | R[j];  // the padded index i whose image is y
+    if (valid == kAllItems<S>) {
+#pragma unroll
+      for (uint32_t j = 0; j < kItems; ++j) pos[j] = atomicAdd(&lds.hist[L[j] >> shift], 1u);
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < kItems; ++j)
+        pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[L[j] >> shift], 1u) : 0u;
     }
     __syncthreads();
     Reservation<S> res;
@@ -390,9 +480,14 @@ __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_ke
       }
     }
     __syncthreads();  // the histogram is cleared
+    if (valid == kAllItems<S>) {
 #pragma unroll
-    for (uint32_t j = 0; j < kItems; ++j)
-      pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[(ii[j] >> a.s) & (digits - 1)], 1u) : 0u;
+      for (uint32_t j = 0; j < kItems; ++j) pos[j] = atomicAdd(&lds.hist[__builtin_amdgcn_ubfe(ii[j], a.s, a.b2)], 1u);
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < kItems; ++j)
+        pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[__builtin_amdgcn_ubfe(ii[j], a.s, a.b2)], 1u) : 0u;
+    }
     __syncthreads();
     Reservation<S> res;
     reserve_runs<EB, S>(lds, res, digits, d1 << a.b2, a.cnt_b);
