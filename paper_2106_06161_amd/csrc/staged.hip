@@ -431,12 +431,12 @@ void staged_first_kernel(const StagedArgs a) {
 }
 
 // Second distribution pass: bucket d1's entries, digit = (i >> s) & (2^b2 -
-// 1), appended to window d1 * 2^b2 + digit.  Work item w covers entries
-// [c * tile, (c + 1) * tile) of bucket w / chunks; items past a bucket's
-// count exit at once (about half of them: a bucket holds the kept share of
-// its capacity).  Consecutive work items share a bucket, so the workgroups
-// in flight append to the same windows and their runs fill whole lines in
-// L2 before they are written back.
+// 1), appended to window d1 * 2^b2 + digit.  Workgroup w covers entries
+// [c * tile, (c + 1) * tile) of bucket w / chunks, c = w mod chunks;
+// workgroups past a bucket's count exit at once (about half of them: a
+// bucket holds the kept share of its capacity).  Consecutive workgroups
+// share a bucket, so the workgroups in flight append to the same windows and
+// their runs fill whole lines in L2 before they are written back.
 template <int EB>
 __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_kernel(const StagedArgs a) {
   using S = DistShape<EB, 2>;
@@ -448,53 +448,50 @@ __global__ __launch_bounds__((DistShape<EB, 2>::kThreads)) void staged_second_ke
   const uint64_t cap_a = uint64_t(1) << (a.k - a.b1);
   const uint64_t cap_b = uint64_t(1) << a.s;
   const uint64_t chunks = cap_a / S::kTile;
-  const uint64_t work = (uint64_t(1) << a.b1) * chunks;
-  for (uint64_t w = blockIdx.x; w < work; w += gridDim.x) {
-    const uint64_t d1 = w / chunks;
-    const uint64_t first = (w % chunks) * S::kTile;
-    const uint32_t cnt = a.cnt_a[d1];
-    if (first >= cnt) continue;  // uniform across the workgroup
-    for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
-    T v[kItems];
-    uint32_t ii[kItems], pos[kItems];
-    uint32_t valid = 0;
-    // the tile's entries from a uniform base and 32-bit lane offsets
-    const uint64_t g0 = d1 * cap_a + first;
-    const uint32_t* __restrict__ ti = a.idx_a + g0;
-    const uint8_t* tv = a.val_a + g0 * EB;
-    const u32x2* __restrict__ tp = reinterpret_cast<const u32x2*>(a.idx_a) + g0;
-    const uint32_t left = cnt - uint32_t(first);  // >= 1
+  const uint64_t d1 = blockIdx.x / chunks;
+  const uint64_t first = (blockIdx.x % chunks) * S::kTile;
+  const uint32_t cnt = a.cnt_a[d1];
+  if (first >= cnt) return;  // uniform across the workgroup
+  for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
+  T v[kItems];
+  uint32_t ii[kItems], pos[kItems];
+  uint32_t valid = 0;
+  // the tile's entries from a uniform base and 32-bit lane offsets
+  const uint64_t g0 = d1 * cap_a + first;
+  const uint32_t* __restrict__ ti = a.idx_a + g0;
+  const uint8_t* tv = a.val_a + g0 * EB;
+  const u32x2* __restrict__ tp = reinterpret_cast<const u32x2*>(a.idx_a) + g0;
+  const uint32_t left = cnt - uint32_t(first);  // >= 1
 #pragma unroll
-    for (uint32_t j = 0; j < kItems; ++j) {
-      const uint32_t off = j * S::kThreads + tid;
-      const bool ok = off < left;
-      valid |= ok ? (1u << j) : 0u;
-      const uint32_t oc = ok ? off : 0u;  // idle lanes re-read the tile's first entry
-      if constexpr (kPairedBuckets<EB>) {
-        const u32x2 r = tp[oc];
-        ii[j] = r.x;
-        v[j] = r.y;
-      } else {
-        ii[j] = ti[oc];
-        v[j] = load_record<EB>(tv + oc * uint32_t(EB), 0);
-      }
-    }
-    __syncthreads();  // the histogram is cleared
-    if (valid == kAllItems<S>) {
-#pragma unroll
-      for (uint32_t j = 0; j < kItems; ++j) pos[j] = atomicAdd(&lds.hist[__builtin_amdgcn_ubfe(ii[j], a.s, a.b2)], 1u);
+  for (uint32_t j = 0; j < kItems; ++j) {
+    const uint32_t off = j * S::kThreads + tid;
+    const bool ok = off < left;
+    valid |= ok ? (1u << j) : 0u;
+    const uint32_t oc = ok ? off : 0u;  // idle lanes re-read the tile's first entry
+    if constexpr (kPairedBuckets<EB>) {
+      const u32x2 r = tp[oc];
+      ii[j] = r.x;
+      v[j] = r.y;
     } else {
-#pragma unroll
-      for (uint32_t j = 0; j < kItems; ++j)
-        pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[__builtin_amdgcn_ubfe(ii[j], a.s, a.b2)], 1u) : 0u;
+      ii[j] = ti[oc];
+      v[j] = load_record<EB>(tv + oc * uint32_t(EB), 0);
     }
-    __syncthreads();
-    Reservation<S> res;
-    reserve_runs<EB, S>(lds, res, digits, d1 << a.b2, a.cnt_b);
-    stage_entries<EB, S>(lds, ii, v, pos, valid, a.s, digits);
-    publish_bases<EB, S>(lds, res, digits, uint32_t(d1 << a.b2), uint32_t(cap_b));
-    write_runs<EB, S, true>(lds, res.count, a.s, digits, a.idx_b, a.val_b);
   }
+  __syncthreads();  // the histogram is cleared
+  if (valid == kAllItems<S>) {
+#pragma unroll
+    for (uint32_t j = 0; j < kItems; ++j) pos[j] = atomicAdd(&lds.hist[__builtin_amdgcn_ubfe(ii[j], a.s, a.b2)], 1u);
+  } else {
+#pragma unroll
+    for (uint32_t j = 0; j < kItems; ++j)
+      pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[__builtin_amdgcn_ubfe(ii[j], a.s, a.b2)], 1u) : 0u;
+  }
+  __syncthreads();
+  Reservation<S> res;
+  reserve_runs<EB, S>(lds, res, digits, d1 << a.b2, a.cnt_b);
+  stage_entries<EB, S>(lds, ii, v, pos, valid, a.s, digits);
+  publish_bases<EB, S>(lds, res, digits, uint32_t(d1 << a.b2), uint32_t(cap_b));
+  write_runs<EB, S, true>(lds, res.count, a.s, digits, a.idx_b, a.val_b);
 }
 
 // Clears the bucket and window counts before a launch's first pass.
@@ -733,7 +730,7 @@ hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hip
   if (a.b2) {
     // second pass: one workgroup per work item (most of the empty ones exit at once)
     const uint64_t work = (uint64_t(1) << a.b1) * ((uint64_t(1) << (a.k - a.b1)) / S2::kTile);
-    const dim3 g2(uint32_t(work < (1u << 24) ? work : (1u << 24)));
+    const dim3 g2{uint32_t(work)};
     hipLaunchKernelGGL((staged_second_kernel<EB>), g2, dim3(S2::kThreads), 0, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
