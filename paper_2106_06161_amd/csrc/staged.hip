@@ -390,7 +390,12 @@ void staged_first_kernel(const StagedArgs a) {
   T v[kItems];
   uint32_t L[kItems], R[kItems], pos[kItems];
   uint32_t valid = load_tile<EB, S>(v, L, R, a, tile);
+  // the cipher runs at a raised wave priority: the SIMDs then issue its VALU
+  // work ahead of the other workgroup's histogram, staging and run writes,
+  // whose few instructions mostly wait on LDS and memory latency anyway
+  __builtin_amdgcn_s_setprio(2);
   vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+  __builtin_amdgcn_s_setprio(0);
   // loads complete on both paths into the loop (see the wait before the
   // stores), so staging never waits on the previous tile's stores
   wait_vector_memory();
@@ -415,7 +420,9 @@ void staged_first_kernel(const StagedArgs a) {
     const bool more = next < tiles;
     if (more) {
       valid = load_tile<EB, S>(v, L, R, a, next);
+      __builtin_amdgcn_s_setprio(2);
       vp_decrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+      __builtin_amdgcn_s_setprio(0);
     }
     publish_bases<EB, S>(lds, res, digits, 0u, uint32_t(cap));
     // the next tile's loads (issued before its cipher) are in; the stores
