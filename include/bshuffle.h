@@ -385,6 +385,9 @@ bs_status bs_clear_tuned_configs(void);
  * bs_shuffle takes the staged form for that class when its workspace allows,
  * see bs_workspace_bytes_staged).  The tuner times the staged form against
  * the best fused shape for single-shuffle classes of 2^20 indices and up.
+ * Like the shapes, a class without an entry takes the nearest listed class
+ * of the same element size below it (so domains above the largest tuned
+ * class keep its choice); below the smallest listed class, the fused form.
  */
 #define BS_AUTOTUNE_VERBOSE 1u
 bs_status bs_autotune(int device, const char *cache_path, uint32_t max_size_bits, uint32_t flags);

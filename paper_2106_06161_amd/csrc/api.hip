@@ -289,12 +289,16 @@ bs_status launch_staged_form(const void* in, void* out, uint64_t n, uint32_t ele
 
 // Whether bs_shuffle takes the staged form for (elem_bytes, k): policy 1
 // always (when the workspace holds its scratch), 2 as the tuned table says
-// (never while a shape is forced with bs_set_config); g_mu held.
+// for the nearest listed class at or below k of that element size, as
+// pick_config takes shapes (never while a shape is forced with
+// bs_set_config); g_mu held.
 bool staged_preferred(uint32_t elem_bytes, uint32_t k) {
   if (g_staged_policy == 1) return true;
   if (g_staged_policy == 0 || g_forced) return false;
-  auto it = g_staged.find({elem_bytes, k});
-  return it != g_staged.end() && it->second;
+  auto it = g_staged.upper_bound({elem_bytes, k});
+  if (it == g_staged.begin()) return false;
+  --it;
+  return it->first.first == elem_bytes && it->second;
 }
 
 // One bs_shuffle launch (n > 0, arguments checked); g_mu held.  The fused

@@ -373,6 +373,11 @@ def test_staged_table_lines(tmp_path):
         assert B.bs_load_tuned_configs(str(t)) == B.BS_OK
         assert B.bs_query_config(0, 4, (1 << 27) + 1) == (0, 0, B.DEPTH_STAGED, 0)
         assert B.bs_query_config(0, 8, (1 << 27) + 1)[2] != B.DEPTH_STAGED
+        # classes without a line take the nearest listed class below them
+        assert B.bs_query_config(0, 4, (1 << 30) + 1) == (0, 0, B.DEPTH_STAGED, 0)
+        assert B.bs_query_config(0, 4, (1 << 26) + 1)[2] != B.DEPTH_STAGED
+        assert B.bs_query_config(0, 8, (1 << 30) + 1)[2] != B.DEPTH_STAGED
+        assert B.bs_query_config(0, 2, (1 << 30) + 1)[2] != B.DEPTH_STAGED
         out = tmp_path / "out.txt"
         assert B.bs_save_tuned_configs(str(out)) == B.BS_OK
         assert [(e["elem_bytes"], e["size_bits"], e["prefer"]) for e in autotune.read_staged(str(out))] == [
