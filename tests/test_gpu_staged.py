@@ -2,7 +2,8 @@
 output as Algorithm 1 for every record size, both parities of k, one and two
 distribution passes, the single-window case, ragged tails, zero and few
 rounds, repeated calls on one scratch and graph replay; the headline
-workload whole."""
+workload whole; 10^9 records and a domain of 2^31 (above the tuned table) on
+oracle slices."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +13,7 @@ import paper_2106_06161_amd as bs
 from paper_2106_06161_amd import binding as B
 from paper_2106_06161_amd import workloads as W
 
-from _helpers import oracle_whole
+from _helpers import check_slices, oracle_whole
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -133,6 +134,43 @@ def test_staged_equals_fused_on_the_headline_workload_whole():
     torch.cuda.synchronize()
     assert torch.equal(y, z)
     assert np.array_equal(y.cpu().numpy(), oracle_whole(x_np, 7, 24))
+
+
+def test_staged_billion_uint32_slices():
+    """n = 10^9 uint32 (domain 2^30: digits 9 + 7, the one-workgroup first
+    pass): a permutation of the input, equal to the oracle on slices at both
+    ends of the padded domain."""
+    n, seed, rounds = 10**9, 1, 24
+    x = torch.arange(n, dtype=torch.int64, device=DEV).to(torch.int32)
+    y = bs.shuffle_staged(x, seed, rounds)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.sort(y)[0], x)
+    del x
+    y_np = y.cpu().numpy().view(np.uint32)
+    domain = 1 << oracle.domain_bits(n)
+    check_slices(np.arange(n, dtype=np.uint32), y_np, seed, rounds, [0, domain - (1 << 20)])
+
+
+def test_bs_shuffle_staged_past_the_tuned_table():
+    """n = 2^30 + 1 uint32 (domain 2^31, digits 9 + 8), above the largest
+    tuned class: bs_shuffle with a workspace that holds the staged scratch
+    takes the staged form, and its output equals the fused kernel's and the
+    oracle's slices."""
+    n, seed, rounds = (1 << 30) + 1, 5, 24
+    assert B.bs_query_config(0, 4, n) == (0, 0, B.DEPTH_STAGED, 0)
+    x = torch.arange(n, dtype=torch.int64, device=DEV).to(torch.int32)
+    ws = bs.make_workspace(B.bs_workspace_bytes_staged(n, 4), device=DEV)
+    y = bs.shuffle(x, seed, rounds, workspace=ws)
+    torch.cuda.synchronize()
+    del ws
+    torch.cuda.empty_cache()
+    z = bs.shuffle(x, seed, rounds)  # default workspace: the fused kernel
+    torch.cuda.synchronize()
+    assert torch.equal(y, z)
+    del x, z
+    y_np = y.cpu().numpy().view(np.uint32)
+    domain = 1 << oracle.domain_bits(n)
+    check_slices(np.arange(n, dtype=np.uint32), y_np, seed, rounds, [0, domain - (1 << 20)])
 
 
 def test_staged_argument_errors_on_device():
