@@ -72,6 +72,7 @@ def test_record_is_used_only_for_matching_sources_and_shape(runs, tmp_path, monk
     assert bench.committed_traffic(digest, LAUNCH)["hbm_bytes_per_launch"] == rec["hbm_bytes_per_launch"]
     assert bench.committed_traffic("0" * 16, LAUNCH) is None
     assert bench.committed_traffic(digest, dict(LAUNCH, grid_mult=0)) is None
+    assert bench.committed_traffic(digest, LAUNCH, rounds=4) is None  # the record is of 24 rounds
 
 
 def test_traffic_record_sums_the_staged_passes(tmp_path):
@@ -97,3 +98,10 @@ def test_traffic_record_sums_the_staged_passes(tmp_path):
     assert rec["fetch_bytes_per_launch"] == pytest.approx((100 + 200 + 300) * 1024 * 2.0)
     assert rec["write_bytes_per_launch"] == pytest.approx((100 + 200 + 300) * 1024 * 1.0)
     assert len(rec["per_kernel_ms_rocprof"]) == 3 and rec["launch"] == launch
+
+
+def test_kernel_label_follows_the_first_pass_shape():
+    staged = {"waves": 0, "items": 0, "depth": bench.DEPTH_STAGED, "grid_mult": 0}
+    assert "staged_first_kernel<4, false, true>" in bench.kernel_label(staged, 24)
+    assert "staged_first_kernel<4, false, false>" in bench.kernel_label(staged, 4)
+    assert bench.kernel_label(staged).count(" + ") == 4
