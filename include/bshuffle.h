@@ -279,6 +279,30 @@ bs_status bs_shuffle_staged(const void *in, void *out, uint64_t n, uint32_t elem
                             uint32_t rounds, void *scratch, size_t scratch_bytes, void *stream);
 
 /*
+ * bs_unshuffle_staged -- exactly bs_unshuffle's output, out[f(i)] = in[rank(i)]
+ * for every kept padded index i (the inverse permutation of the shuffle,
+ * Sec. 3.2 and Algorithm 1), computed by streaming passes instead of
+ * scattered writes: per tile of padded indices the forward cipher and the
+ * kept images f(i) in index order; a scan of the tiles' kept counts (a
+ * tile's records are then the consecutive in[] entries from its first rank);
+ * the images with their records distributed into buckets by the high bits
+ * of f(i), as bs_shuffle_staged distributes by i; and the place pass, where
+ * the positions f(i) fill every slot below n, so each window is written in
+ * order.  Memory traffic per record: the kept images written and read (4 + 4),
+ * then bs_shuffle_staged's passes (6 * elem_bytes + 12).
+ *
+ *   scratch  device memory of at least bs_unshuffle_staged_scratch_bytes(n,
+ *            elem_bytes) bytes: bs_staged_scratch_bytes plus 4 bytes per
+ *            padded index and 8 per tile of padded indices; other conditions
+ *            and errors as for bs_shuffle_staged.
+ * Covers the domains bs_shuffle_staged covers (bs_unshuffle_staged_scratch_bytes
+ * returns 0 and bs_unshuffle_staged BS_EINVAL outside them).
+ */
+size_t bs_unshuffle_staged_scratch_bytes(uint64_t n, uint32_t elem_bytes);
+bs_status bs_unshuffle_staged(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                              uint32_t rounds, void *scratch, size_t scratch_bytes, void *stream);
+
+/*
  * The linear congruential bijection of Sec. 3.1 as the shuffle's f, for
  * comparison with VariablePhilox (Sec. 5 reports its poor quality: at n = 5
  * its chi-square statistic is in the hundreds of thousands).

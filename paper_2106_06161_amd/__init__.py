@@ -34,6 +34,8 @@ from .binding import (  # noqa: F401
     staged_scratch_bytes,
     unshuffle,
     unshuffle_inverse,
+    unshuffle_staged,
+    unshuffle_staged_scratch_bytes,
     workspace_bytes,
     workspace_error,
     workspace_error_async,

@@ -64,6 +64,8 @@ _SIGNATURES = {
     "bs_workspace_bytes_staged": (_sz, [_u64, _u32]),
     "bs_probe_set_staged_policy": (_i32, [_u32]),
     "bs_shuffle_staged": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
+    "bs_unshuffle_staged_scratch_bytes": (_sz, [_u64, _u32]),
+    "bs_unshuffle_staged": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _vp, _sz, _vp]),
     "bs_autotune": (_i32, [ctypes.c_int, ctypes.c_char_p, _u32, _u32]),
     "bs_load_tuned_configs": (_i32, [ctypes.c_char_p]),
     "bs_save_tuned_configs": (_i32, [ctypes.c_char_p]),
@@ -555,6 +557,49 @@ def shuffle_staged(x, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, scratch
         st = bs_shuffle_staged(x.data_ptr(), out.data_ptr(), n, eb, seed, rounds, scratch.data_ptr(),
                                scratch.numel() * scratch.element_size(), _stream_ptr(x, stream))
     _check(st, "bs_shuffle_staged")
+    return out
+
+
+def bs_unshuffle_staged_scratch_bytes(n: int, elem_bytes: int) -> int:
+    return int(lib().bs_unshuffle_staged_scratch_bytes(n, elem_bytes))
+
+
+def bs_unshuffle_staged(in_ptr, out_ptr, n, elem_bytes, seed, rounds, scratch, scratch_bytes, stream) -> int:
+    return int(lib().bs_unshuffle_staged(in_ptr, out_ptr, n, elem_bytes, seed & (2**64 - 1), rounds, scratch,
+                                         scratch_bytes, stream))
+
+
+def unshuffle_staged_scratch_bytes(n: int, elem_bytes: int) -> int:
+    """Scratch bytes bs_unshuffle_staged needs (0: the staged form does not cover this size)."""
+    return bs_unshuffle_staged_scratch_bytes(n, elem_bytes)
+
+
+def unshuffle_staged(y, seed: int, rounds: int = DEFAULT_ROUNDS, out=None, scratch=None, stream=None):
+    """bs_unshuffle's result (the inverse of shuffle with the same seed and
+    rounds) through the staged passes; scratch is a uint8 GPU tensor of at
+    least unshuffle_staged_scratch_bytes(n, elem_bytes) bytes (allocated here
+    when None)."""
+    import torch
+
+    _require_device(y, "y")
+    if out is None:
+        out = torch.empty_like(y)
+    _require_device(out, "out")
+    if out.shape != y.shape or out.dtype != y.dtype or out.device != y.device:
+        raise ValueError("out must match y in shape, dtype and device")
+    n, eb = _records(y)
+    if n == 0:
+        return out
+    need = bs_unshuffle_staged_scratch_bytes(n, eb)
+    if need == 0:
+        raise BShuffleError(BS_EINVAL, "bs_unshuffle_staged: size outside the staged form")
+    if scratch is None:
+        scratch = torch.empty(need, dtype=torch.uint8, device=y.device)
+    _require_device(scratch, "scratch")
+    with torch.cuda.device(y.device):
+        st = bs_unshuffle_staged(y.data_ptr(), out.data_ptr(), n, eb, seed, rounds, scratch.data_ptr(),
+                                 scratch.numel() * scratch.element_size(), _stream_ptr(y, stream))
+    _check(st, "bs_unshuffle_staged")
     return out
 
 

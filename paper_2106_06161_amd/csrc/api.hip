@@ -260,9 +260,9 @@ StagedLayout staged_layout(uint64_t n, uint32_t elem_bytes) {
   return l;
 }
 
-// The staged form's launch (arguments checked, scratch of l.total bytes).
-bs_status launch_staged_form(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
-                             uint32_t rounds, uint8_t* scratch, const StagedLayout& l, uint32_t cus, hipStream_t s) {
+// The staged form's kernel arguments over a scratch of l.total bytes.
+bsd::StagedArgs staged_args(const void* in, void* out, uint64_t n, uint64_t seed, uint32_t rounds, uint8_t* scratch,
+                            const StagedLayout& l) {
   bsd::SingleArgs c = {};
   setup_cipher(c, n, seed, rounds);
   bsd::StagedArgs a = {};
@@ -283,6 +283,13 @@ bs_status launch_staged_form(const void* in, void* out, uint64_t n, uint32_t ele
   a.idx_b = reinterpret_cast<uint16_t*>(scratch + l.idx_b);
   a.val_b = scratch + l.val_b;
   std::copy(std::begin(c.key), std::end(c.key), std::begin(a.key));
+  return a;
+}
+
+// The staged form's launch (arguments checked, scratch of l.total bytes).
+bs_status launch_staged_form(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                             uint32_t rounds, uint8_t* scratch, const StagedLayout& l, uint32_t cus, hipStream_t s) {
+  const bsd::StagedArgs a = staged_args(in, out, n, seed, rounds, scratch, l);
   const hipError_t e = bsd::launch_staged(a, elem_bytes, cus, s);
   return e == hipSuccess ? BS_OK : hip_fail(e);
 }
@@ -947,6 +954,64 @@ extern "C" bs_status bs_shuffle_staged(const void* in, void* out, uint64_t n, ui
   if (cst != BS_OK) return cst;
   return launch_staged_form(in, out, n, elem_bytes, seed, rounds, static_cast<uint8_t*>(scratch), l, cus,
                             static_cast<hipStream_t>(stream));
+}
+
+// Scratch of the staged un-shuffle: the staged form's, then the kept images
+// (one word per padded index, at least one tile), the tiles' kept counts and
+// their first ranks.
+struct UnshuffleLayout {
+  StagedLayout l;
+  size_t keys = 0, cnt = 0, base = 0, total = 0;
+  uint32_t tiles = 0;
+};
+
+UnshuffleLayout unshuffle_staged_layout(uint64_t n, uint32_t elem_bytes) {
+  UnshuffleLayout u;
+  u.l = staged_layout(n, elem_bytes);
+  if (!u.l.ok) return u;
+  const uint64_t domain = uint64_t(1) << u.l.k;
+  const uint64_t tile = bsd::unshuffle_key_tile(elem_bytes);
+  u.tiles = uint32_t(domain > tile ? domain / tile : 1u);
+  u.keys = u.l.total;
+  u.cnt = u.keys + align256(std::max(domain, tile) * 4);
+  u.base = u.cnt + align256(uint64_t(u.tiles) * 4);
+  u.total = u.base + align256(uint64_t(u.tiles) * 4);
+  return u;
+}
+
+extern "C" size_t bs_unshuffle_staged_scratch_bytes(uint64_t n, uint32_t elem_bytes) {
+  if (n == 0) return 0;
+  const UnshuffleLayout u = unshuffle_staged_layout(n, elem_bytes);
+  return u.l.ok ? u.total : 0;
+}
+
+extern "C" bs_status bs_unshuffle_staged(const void* in, void* out, uint64_t n, uint32_t elem_bytes, uint64_t seed,
+                                         uint32_t rounds, void* scratch, size_t scratch_bytes, void* stream) {
+  const bs_status st = check_single_args(in, out, n, elem_bytes, rounds);
+  if (st != BS_OK || n == 0) return st;
+  const UnshuffleLayout u = unshuffle_staged_layout(n, elem_bytes);
+  if (!u.l.ok) return BS_EINVAL;
+  if (!scratch || reinterpret_cast<uintptr_t>(scratch) % 256) return BS_EINVAL;
+  if (scratch_bytes < u.total) return BS_ENOMEM;
+  {
+    const uintptr_t sc = reinterpret_cast<uintptr_t>(scratch);
+    const uintptr_t x = reinterpret_cast<uintptr_t>(in), y = reinterpret_cast<uintptr_t>(out);
+    const uint64_t bytes = n * elem_bytes;
+    if ((sc < x + bytes && x < sc + u.total) || (sc < y + bytes && y < sc + u.total)) return BS_EALIAS;
+  }
+  int dev = 0;
+  uint32_t cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  std::lock_guard<std::mutex> lock(g_mu);
+  const bs_status cst = device_cus(dev, &cus);
+  if (cst != BS_OK) return cst;
+  uint8_t* sb = static_cast<uint8_t*>(scratch);
+  const bsd::StagedArgs a = staged_args(in, out, n, seed, rounds, sb, u.l);
+  e = bsd::launch_unshuffle_staged(a, reinterpret_cast<uint32_t*>(sb + u.keys), reinterpret_cast<uint32_t*>(sb + u.cnt),
+                                   reinterpret_cast<uint32_t*>(sb + u.base), elem_bytes, cus,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BS_OK : hip_fail(e);
 }
 
 extern "C" size_t bs_workspace_bytes_staged(uint64_t n, uint32_t elem_bytes) {

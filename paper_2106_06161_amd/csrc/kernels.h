@@ -157,6 +157,13 @@ hipError_t launch_unshuffle_inverse(const InverseArgs& a, uint32_t elem_bytes, h
 uint32_t staged_window_bits(uint32_t elem_bytes);
 bool staged_digits(uint32_t k, uint32_t elem_bytes, uint32_t* s, uint32_t* b1, uint32_t* b2);
 hipError_t launch_staged(const StagedArgs& a, uint32_t elem_bytes, uint32_t num_cus, hipStream_t stream);
+// The staged un-shuffle: the staged form's passes keyed by the output
+// position f(i) of every kept padded index, with the record read at rank(i).
+// keys: max(2^k, tile) words; tile_cnt, tile_base: one word per tile of
+// unshuffle_key_tile(elem_bytes) padded indices.
+uint32_t unshuffle_key_tile(uint32_t elem_bytes);
+hipError_t launch_unshuffle_staged(const StagedArgs& a, uint32_t* keys, uint32_t* tile_cnt, uint32_t* tile_base,
+                                   uint32_t elem_bytes, uint32_t num_cus, hipStream_t stream);
 
 bool config_supported(const LaunchConfig& cfg);
 // The shape a batched launch runs: cfg when compiled, else the default

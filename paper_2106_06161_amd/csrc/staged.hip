@@ -687,6 +687,113 @@ __global__ __launch_bounds__(kPlaceThreads, 8) void staged_place_kernel(const St
   }
 }
 
+// The staged un-shuffle (the inverse of the shuffle, out[f(i)] = in[rank(i)]
+// for every kept padded index i): the same distribution passes, keyed by the
+// output position f(i) instead of the padded index.  Output positions are
+// dense in [0, n), so the place pass's ranks are the positions themselves.
+// First, per tile of TK padded indices: the forward cipher, the kept images
+// compacted in index order at keys[tile * TK + e] and the tile's count.
+template <int EB, bool ODD>
+__global__ __launch_bounds__(512) void staged_unshuffle_keys_kernel(const StagedArgs a, uint32_t* __restrict__ keys,
+                                                                    uint32_t* __restrict__ tile_cnt) {
+  constexpr uint32_t TK = DistShape<EB, 3>::kTile;
+  constexpr uint32_t kWaves = 8, kItems = TK / 512u;
+  __shared__ uint32_t wave_total[kWaves];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint64_t domain = uint64_t(1) << a.k;
+  const uint64_t t = blockIdx.x;
+  // wave w holds indices [w * 64 * kItems, (w + 1) * 64 * kItems) of the
+  // tile, item j the 64 consecutive ones from j * 64: index order is (wave,
+  // item, lane)
+  const uint64_t first = t * TK + uint64_t(wave) * (64u * kItems) + lane;
+  const uint32_t wmask24 = a.cs.wmask & 0xFFFFFFu;
+  uint32_t L[kItems], R[kItems];
+#pragma unroll
+  for (uint32_t j = 0; j < kItems; ++j) {
+    const uint64_t x = first + 64u * j;
+    L[j] = uint32_t(x >> a.cs.r) & wmask24;
+    R[j] = uint32_t(x);
+  }
+  vp_encrypt<ODD, kItems>(L, R, a.cs, a.rounds, a.key);
+  uint32_t y[kItems], at[kItems], keep_bits = 0, run = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kItems; ++j) {
+    y[j] = (L[j] << a.cs.r) | (R[j] & a.cs.rmask);
+    const bool keep = first + 64u * j < domain && uint64_t(y[j]) < a.n;
+    const uint64_t m = __ballot(keep);
+    at[j] = run + __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    run += uint32_t(__builtin_popcountll(m));
+    keep_bits |= keep ? (1u << j) : 0u;
+  }
+  if (lane == 0) wave_total[wave] = run;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    const uint32_t c = wave_total[w];
+    before += w < wave ? c : 0u;
+    total += c;
+  }
+  uint32_t* __restrict__ kt = keys + t * TK;
+#pragma unroll
+  for (uint32_t j = 0; j < kItems; ++j)
+    if ((keep_bits >> j) & 1u) kt[before + at[j]] = y[j];
+  if (tid == 0) tile_cnt[t] = total;
+}
+
+// Then per key tile (one workgroup each): its kept images with the records
+// in[tile_base[t] + e] (the tile's ranks are consecutive, so the reads are
+// too), distributed by the image's first digit like the first pass.
+template <int EB>
+__global__ __launch_bounds__((DistShape<EB, 3>::kThreads)) void staged_unshuffle_first_kernel(
+    const StagedArgs a, const uint32_t* __restrict__ keys, const uint32_t* __restrict__ tile_cnt,
+    const uint32_t* __restrict__ tile_base) {
+  using S = DistShape<EB, 3>;
+  using T = typename Payload<EB>::T;
+  constexpr uint32_t kItems = S::kItems;
+  __shared__ DistLds<EB, S> lds;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t t = blockIdx.x;
+  const uint32_t cnt = global_keys(tile_cnt)[t];
+  if (cnt == 0) return;  // uniform across the workgroup
+  const uint32_t base = global_keys(tile_base)[t];
+  const uint32_t digits = 1u << a.b1;
+  const uint32_t shift = a.k - a.b1;
+  const uint64_t cap = uint64_t(1) << shift;
+  const bool windows = a.b2 == 0;
+  void* idx_out = windows ? static_cast<void*>(a.idx_b) : static_cast<void*>(a.idx_a);
+  uint8_t* val_out = windows ? a.val_b : a.val_a;
+  uint32_t* counts = windows ? a.cnt_b : a.cnt_a;
+  for (uint32_t d = tid; d < digits; d += S::kThreads) lds.hist[d] = 0;
+  T v[kItems];
+  uint32_t ii[kItems], pos[kItems];
+  uint32_t valid = 0;
+  const uint32_t* __restrict__ kt = keys + t * S::kTile;
+  const uint8_t* src = a.in + uint64_t(base) * EB;
+#pragma unroll
+  for (uint32_t j = 0; j < kItems; ++j) {
+    const uint32_t off = j * S::kThreads + tid;
+    const bool ok = off < cnt;
+    valid |= ok ? (1u << j) : 0u;
+    const uint32_t oc = ok ? off : 0u;  // idle lanes re-read the tile's first entry
+    ii[j] = kt[oc];
+    v[j] = load_record<EB>(src + oc * uint32_t(EB), 0);
+  }
+  __syncthreads();  // the histogram is cleared
+#pragma unroll
+  for (uint32_t j = 0; j < kItems; ++j)
+    pos[j] = ((valid >> j) & 1u) ? atomicAdd(&lds.hist[ii[j] >> shift], 1u) : 0u;
+  __syncthreads();
+  Reservation<S> res;
+  reserve_runs<EB, S>(lds, res, digits, 0, counts);
+  stage_entries<EB, S>(lds, ii, v, pos, valid, shift, digits);
+  publish_bases<EB, S>(lds, res, digits, 0u, uint32_t(cap));
+  if (windows)
+    write_runs<EB, S, true>(lds, res.count, shift, digits, idx_out, val_out);
+  else
+    write_runs<EB, S, false>(lds, res.count, shift, digits, idx_out, val_out);
+}
+
 // Workgroups of fn that stay resident on the device at once.
 uint32_t resident_groups(const void* fn, uint32_t threads, uint32_t num_cus) {
   int per_cu = 0;
@@ -707,8 +814,10 @@ void launch_first(const StagedArgs& a, uint32_t num_cus, hipStream_t stream) {
 }
 
 template <int EB>
+hipError_t launch_staged_rest(const StagedArgs& a, uint32_t num_cus, hipStream_t stream);
+
+template <int EB>
 hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hipStream_t stream) {
-  using S2 = DistShape<EB, 2>;
   const uint32_t zero_groups = std::max(1u, std::min(256u, (1u << (a.b1 + a.b2)) / 256u));
   hipLaunchKernelGGL(staged_zero_kernel, dim3(zero_groups), dim3(256), 0, stream, a);
   // the two-workgroups-per-CU first pass once the inverse cipher is long
@@ -732,8 +841,16 @@ hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hip
   } else {
     launch_first<EB, true, false>(a, num_cus, stream);
   }
-  hipError_t e = hipGetLastError();
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_staged_rest<EB>(a, num_cus, stream);
+}
+
+// The passes after the first: second distribution, window scan, place.
+template <int EB>
+hipError_t launch_staged_rest(const StagedArgs& a, uint32_t num_cus, hipStream_t stream) {
+  using S2 = DistShape<EB, 2>;
+  hipError_t e;
   if (a.b2) {
     // second pass: one workgroup per work item (most of the empty ones exit at once)
     const uint64_t work = (uint64_t(1) << a.b1) * ((uint64_t(1) << (a.k - a.b1)) / S2::kTile);
@@ -753,7 +870,61 @@ hipError_t launch_staged_eb(const StagedArgs& a, bool odd, uint32_t num_cus, hip
   return hipGetLastError();
 }
 
+template <int EB>
+hipError_t launch_unshuffle_eb(const StagedArgs& a, bool odd, uint32_t* keys, uint32_t* tile_cnt,
+                               uint32_t* tile_base, uint32_t num_cus, hipStream_t stream) {
+  using S = DistShape<EB, 3>;
+  const uint64_t domain = uint64_t(1) << a.k;
+  const uint32_t tiles = uint32_t(domain > S::kTile ? domain / S::kTile : 1u);  // a power of two
+  const uint32_t zero_groups = std::max(1u, std::min(256u, (1u << (a.b1 + a.b2)) / 256u));
+  hipLaunchKernelGGL(staged_zero_kernel, dim3(zero_groups), dim3(256), 0, stream, a);
+  if (odd)
+    hipLaunchKernelGGL((staged_unshuffle_keys_kernel<EB, true>), dim3(tiles), dim3(512), 0, stream, a, keys,
+                       tile_cnt);
+  else
+    hipLaunchKernelGGL((staged_unshuffle_keys_kernel<EB, false>), dim3(tiles), dim3(512), 0, stream, a, keys,
+                       tile_cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the tiles' first ranks: the window scan over the tile counts
+  StagedArgs sc = a;
+  sc.cnt_b = tile_cnt;
+  sc.base_b = tile_base;
+  sc.b1 = uint32_t(__builtin_ctz(tiles));
+  sc.b2 = 0;
+  hipLaunchKernelGGL(staged_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, sc);
+  hipLaunchKernelGGL((staged_unshuffle_first_kernel<EB>), dim3(tiles), dim3(S::kThreads), 0, stream, a, keys,
+                     tile_cnt, tile_base);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_staged_rest<EB>(a, num_cus, stream);
+}
+
 }  // namespace
+
+uint32_t unshuffle_key_tile(uint32_t elem_bytes) {
+  switch (elem_bytes) {
+    case 1: return DistShape<1, 3>::kTile;
+    case 2: return DistShape<2, 3>::kTile;
+    case 4: return DistShape<4, 3>::kTile;
+    case 8: return DistShape<8, 3>::kTile;
+    case 16: return DistShape<16, 3>::kTile;
+    default: return 0;
+  }
+}
+
+hipError_t launch_unshuffle_staged(const StagedArgs& a, uint32_t* keys, uint32_t* tile_cnt, uint32_t* tile_base,
+                                   uint32_t elem_bytes, uint32_t num_cus, hipStream_t stream) {
+  const bool odd = ((a.cs.w + a.cs.r) & 1u) != 0;
+  switch (elem_bytes) {
+    case 1: return launch_unshuffle_eb<1>(a, odd, keys, tile_cnt, tile_base, num_cus, stream);
+    case 2: return launch_unshuffle_eb<2>(a, odd, keys, tile_cnt, tile_base, num_cus, stream);
+    case 4: return launch_unshuffle_eb<4>(a, odd, keys, tile_cnt, tile_base, num_cus, stream);
+    case 8: return launch_unshuffle_eb<8>(a, odd, keys, tile_cnt, tile_base, num_cus, stream);
+    case 16: return launch_unshuffle_eb<16>(a, odd, keys, tile_cnt, tile_base, num_cus, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 uint32_t staged_window_bits(uint32_t elem_bytes) {
   switch (elem_bytes) {

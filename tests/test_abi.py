@@ -350,6 +350,32 @@ def test_staged_scratch_sizes_and_argument_checks():
     assert f(FAKE_IN, FAKE_OUT, 0, 4, 1, 24, None, 0, None) == B.BS_OK
 
 
+def test_unshuffle_staged_scratch_sizes_and_argument_checks():
+    # the staged form's scratch, then one key word per padded index (2^28)
+    # and two words per tile of 8,192 padded indices (2^15 tiles)
+    n = (1 << 27) + 1
+    assert B.bs_unshuffle_staged_scratch_bytes(n, 4) == B.bs_staged_scratch_bytes(n, 4) + 4 * (1 << 28) + 8 * (1 << 15)
+    # 16-byte records: tiles of 4,096 padded indices
+    assert B.bs_unshuffle_staged_scratch_bytes(n, 16) == (B.bs_staged_scratch_bytes(n, 16) + 4 * (1 << 28)
+                                                           + 8 * (1 << 16))
+    # a domain smaller than one tile: one tile's key words, one count and prefix
+    assert B.bs_unshuffle_staged_scratch_bytes(1000, 4) == B.bs_staged_scratch_bytes(1000, 4) + 4 * 8192 + 2 * 256
+    assert B.bs_unshuffle_staged_scratch_bytes(0, 4) == 0
+    assert B.bs_unshuffle_staged_scratch_bytes(1000, 3) == 0
+    assert B.bs_unshuffle_staged_scratch_bytes((1 << 32) + 1, 4) == 0
+    n = 1 << 20
+    need = B.bs_unshuffle_staged_scratch_bytes(n, 4)
+    f = B.bs_unshuffle_staged
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, None, need, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, 1 << 42, need - 1, None) == B.BS_ENOMEM
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, (1 << 42) + 64, need, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 24, FAKE_IN - 256, need, None) == B.BS_EALIAS
+    assert f(FAKE_IN, FAKE_OUT, n, 3, 1, 24, 1 << 42, need, None) == B.BS_EELEM
+    assert f(FAKE_IN, FAKE_OUT, n, 4, 1, 65, 1 << 42, need, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, (1 << 32) + 1, 4, 1, 24, 1 << 42, 1 << 40, None) == B.BS_EINVAL
+    assert f(FAKE_IN, FAKE_OUT, 0, 4, 1, 24, None, 0, None) == B.BS_OK
+
+
 def test_staged_workspace_bytes_and_policy():
     n = (1 << 27) + 1
     fused = B.bs_workspace_bytes(n, 0, 4)

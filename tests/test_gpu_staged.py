@@ -3,7 +3,8 @@ output as Algorithm 1 for every record size, both parities of k, one and two
 distribution passes, the single-window case, ragged tails, zero and few
 rounds, repeated calls on one scratch and graph replay; the headline
 workload whole; 10^9 records and a domain of 2^31 (above the tuned table) on
-oracle slices."""
+oracle slices.  bs_unshuffle_staged (the same passes keyed by output
+position) against the oracle's shuffle."""
 import numpy as np
 import pytest
 import torch
@@ -171,6 +172,46 @@ def test_bs_shuffle_staged_past_the_tuned_table():
     y_np = y.cpu().numpy().view(np.uint32)
     domain = 1 << oracle.domain_bits(n)
     check_slices(np.arange(n, dtype=np.uint32), y_np, seed, rounds, [0, domain - (1 << 20)])
+
+
+def unstaged(y_np, seed, rounds):
+    y = to_dev(y_np)
+    x = bs.unshuffle_staged(y, seed, rounds)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().view(y_np.dtype).reshape(y_np.shape)
+
+
+# the staged un-shuffle inverts the oracle's shuffle: every record size, one
+# and two distribution passes, both parities of k, a domain smaller than one
+# key tile, ragged tails
+UNSHUFFLE_CASES = [(1, 4), (1000, 4), (100_000, 4), ((1 << 20) + 1, 4), ((1 << 23) + 1, 4), ((1 << 24) + 1, 4),
+                   (70_001, 1), ((1 << 22) + 1, 1), (100_003, 2), ((1 << 23) + 7, 2), (65_537, 8),
+                   ((1 << 21) + 1, 8), (3000, 16), ((1 << 20) + 1, 16)]
+
+
+@pytest.mark.parametrize("n,eb", UNSHUFFLE_CASES)
+def test_unshuffle_staged_inverts_the_oracle_shuffle(n, eb):
+    x = records(n, eb, seed=n + 2 * eb)
+    y = oracle.shuffle(x, 500 + n, 24)
+    assert np.array_equal(unstaged(y, 500 + n, 24), x), (n, eb)
+
+
+@pytest.mark.parametrize("rounds", [0, 1, 4, 9, 16])
+def test_unshuffle_staged_round_counts(rounds):
+    x = records((1 << 22) + 3, 4, seed=rounds)
+    assert np.array_equal(unstaged(oracle.shuffle(x, 13, rounds), 13, rounds), x)
+
+
+def test_unshuffle_staged_headline_equals_the_scatter_form():
+    """n = 2^27 + 1 uniform uint32, seed 7, 24 rounds: the staged un-shuffle of
+    the shuffle is the input, and equals bs_unshuffle's output."""
+    x = torch.from_numpy(W.uniform_u32((1 << 27) + 1, seed=7)).to(DEV)
+    y = bs.shuffle(x, 7, 24)
+    z = bs.unshuffle_staged(y, 7, 24)
+    w = bs.unshuffle(y, 7, 24)
+    torch.cuda.synchronize()
+    assert torch.equal(z, x)
+    assert torch.equal(w, x)
 
 
 def test_staged_argument_errors_on_device():
