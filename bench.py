@@ -507,7 +507,19 @@ def bench_fusion(torch, bs, B, W, dev, stream, timer, rounds, n, x=None, y=None)
     res["unshuffle_inverse_Gelem_s"] = n / t / 1e9
     if not torch.equal(z, x):
         raise RuntimeError(f"unshuffle_inverse did not invert the shuffle at n={n}")
-    del idx, z, inv_scratch
+    del inv_scratch
+    # and through the staged passes keyed by output position
+    need = bs.unshuffle_staged_scratch_bytes(n, 4)
+    if need:
+        un_scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+        z.zero_()
+        t = timer.run(lambda: bs.unshuffle_staged(ref, SEED, rounds, out=z, scratch=un_scratch), 5)
+        res["unshuffle_staged_ms"] = t * 1e3
+        res["unshuffle_staged_Gelem_s"] = n / t / 1e9
+        if not torch.equal(z, x):
+            raise RuntimeError(f"unshuffle_staged did not invert the shuffle at n={n}")
+        del un_scratch
+    del idx, z
     perm = torch.randperm(n, device=dev, dtype=torch.int64).to(torch.int32)
     t = timer.run(lambda: B.bs_probe_gather(x.data_ptr(), n, y.data_ptr(), perm.data_ptr(), n, 4, sp), 5)
     res["gather_index_array_ms"] = t * 1e3
