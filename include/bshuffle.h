@@ -203,7 +203,8 @@ bs_status bs_permutation(void *out_idx, uint64_t n, uint32_t index_bytes, uint64
  * out[f(i)] = in[rank(i)] for every kept padded index i (VariablePhilox is
  * a bijection, Sec. 3.2; its inverse permutation undoes the shuffle), so
  * bs_unshuffle(bs_shuffle(x)) == x.  Reads are coalesced, writes scattered.
- * Arguments and errors as for bs_shuffle.
+ * Arguments and errors as for bs_shuffle.  bs_unshuffle_staged computes the
+ * same output with streaming passes only (below).
  */
 bs_status bs_unshuffle(const void *in, void *out, uint64_t n, uint32_t elem_bytes, uint64_t seed, uint32_t rounds,
                        void *workspace, size_t workspace_bytes, void *stream);

@@ -214,6 +214,32 @@ def test_unshuffle_staged_headline_equals_the_scatter_form():
     assert torch.equal(w, x)
 
 
+def test_unshuffle_staged_under_graph_replay():
+    """Captured once, replayed with other work on the same scratch between
+    replays: every replay inverts the oracle's shuffle."""
+    n = (1 << 23) + 1
+    x_np = records(n, 4, seed=12)
+    y = to_dev(oracle.shuffle(x_np, 78, 24))
+    z = torch.empty_like(y)
+    scratch = torch.empty(bs.unshuffle_staged_scratch_bytes(n, 4), dtype=torch.uint8, device=DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bs.unshuffle_staged(y, 78, 24, out=z, scratch=scratch)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        bs.unshuffle_staged(y, 78, 24, out=z, scratch=scratch)
+    for rep in range(4):
+        z.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(z.cpu().numpy().view(np.uint32), x_np), rep
+        bs.unshuffle_staged(y[: n // 2], 5, 24, out=z[: n // 2], scratch=scratch)  # eager work between replays
+        torch.cuda.synchronize()
+
+
 def test_staged_argument_errors_on_device():
     x = torch.zeros(1 << 20, dtype=torch.int32, device=DEV)
     y = torch.empty_like(x)
