@@ -693,10 +693,16 @@ __global__ __launch_bounds__(kPlaceThreads, 8) void staged_place_kernel(const St
 // dense in [0, n), so the place pass's ranks are the positions themselves.
 // First, per tile of TK padded indices: the forward cipher, the kept images
 // compacted in index order at keys[tile * TK + e] and the tile's count.
+template <int EB>
+constexpr uint32_t kKeyTile = DistShape<EB, 3>::kTile;
+// key tiles per distribution tile of the first pass's large shape (1 or 2)
+template <int EB>
+constexpr uint32_t kKeysPerTile = DistShape<EB, 1>::kTile / kKeyTile<EB>;
+
 template <int EB, bool ODD>
 __global__ __launch_bounds__(512) void staged_unshuffle_keys_kernel(const StagedArgs a, uint32_t* __restrict__ keys,
                                                                     uint32_t* __restrict__ tile_cnt) {
-  constexpr uint32_t TK = DistShape<EB, 3>::kTile;
+  constexpr uint32_t TK = kKeyTile<EB>;
   constexpr uint32_t kWaves = 8, kItems = TK / 512u;
   __shared__ uint32_t wave_total[kWaves];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -741,20 +747,24 @@ __global__ __launch_bounds__(512) void staged_unshuffle_keys_kernel(const Staged
   if (tid == 0) tile_cnt[t] = total;
 }
 
-// Then per key tile (one workgroup each): its kept images with the records
-// in[tile_base[t] + e] (the tile's ranks are consecutive, so the reads are
+// Then per kKeysPerTile consecutive key tiles (one workgroup each, the first
+// pass's large tile shape): their kept images with the records
+// in[tile_base[t] + e] (the tiles' ranks are consecutive, so the reads are
 // too), distributed by the image's first digit like the first pass.
 template <int EB>
-__global__ __launch_bounds__((DistShape<EB, 3>::kThreads)) void staged_unshuffle_first_kernel(
+__global__ __launch_bounds__((DistShape<EB, 1>::kThreads)) void staged_unshuffle_first_kernel(
     const StagedArgs a, const uint32_t* __restrict__ keys, const uint32_t* __restrict__ tile_cnt,
-    const uint32_t* __restrict__ tile_base) {
-  using S = DistShape<EB, 3>;
+    const uint32_t* __restrict__ tile_base, uint32_t tiles) {
+  using S = DistShape<EB, 1>;
   using T = typename Payload<EB>::T;
   constexpr uint32_t kItems = S::kItems;
+  constexpr uint32_t TK = kKeyTile<EB>;
   __shared__ DistLds<EB, S> lds;
   const uint32_t tid = threadIdx.x;
-  const uint64_t t = blockIdx.x;
-  const uint32_t cnt = global_keys(tile_cnt)[t];
+  const uint64_t t = uint64_t(blockIdx.x) * kKeysPerTile<EB>;
+  const uint32_t c0 = global_keys(tile_cnt)[t];
+  const uint32_t c1 = kKeysPerTile<EB> == 2 && t + 1 < tiles ? global_keys(tile_cnt)[t + 1] : 0u;
+  const uint32_t cnt = c0 + c1;
   if (cnt == 0) return;  // uniform across the workgroup
   const uint32_t base = global_keys(tile_base)[t];
   const uint32_t digits = 1u << a.b1;
@@ -768,7 +778,8 @@ __global__ __launch_bounds__((DistShape<EB, 3>::kThreads)) void staged_unshuffle
   T v[kItems];
   uint32_t ii[kItems], pos[kItems];
   uint32_t valid = 0;
-  const uint32_t* __restrict__ kt = keys + t * S::kTile;
+  // entry e: key tile t's e-th image, then tile t + 1's (e - c0)-th
+  const uint32_t* __restrict__ kt = keys + t * TK;
   const uint8_t* src = a.in + uint64_t(base) * EB;
 #pragma unroll
   for (uint32_t j = 0; j < kItems; ++j) {
@@ -776,7 +787,7 @@ __global__ __launch_bounds__((DistShape<EB, 3>::kThreads)) void staged_unshuffle
     const bool ok = off < cnt;
     valid |= ok ? (1u << j) : 0u;
     const uint32_t oc = ok ? off : 0u;  // idle lanes re-read the tile's first entry
-    ii[j] = kt[oc];
+    ii[j] = kt[oc < c0 ? oc : TK + (oc - c0)];
     v[j] = load_record<EB>(src + oc * uint32_t(EB), 0);
   }
   __syncthreads();  // the histogram is cleared
@@ -873,9 +884,9 @@ hipError_t launch_staged_rest(const StagedArgs& a, uint32_t num_cus, hipStream_t
 template <int EB>
 hipError_t launch_unshuffle_eb(const StagedArgs& a, bool odd, uint32_t* keys, uint32_t* tile_cnt,
                                uint32_t* tile_base, uint32_t num_cus, hipStream_t stream) {
-  using S = DistShape<EB, 3>;
+  using S = DistShape<EB, 1>;
   const uint64_t domain = uint64_t(1) << a.k;
-  const uint32_t tiles = uint32_t(domain > S::kTile ? domain / S::kTile : 1u);  // a power of two
+  const uint32_t tiles = uint32_t(domain > kKeyTile<EB> ? domain / kKeyTile<EB> : 1u);  // a power of two
   const uint32_t zero_groups = std::max(1u, std::min(256u, (1u << (a.b1 + a.b2)) / 256u));
   hipLaunchKernelGGL(staged_zero_kernel, dim3(zero_groups), dim3(256), 0, stream, a);
   if (odd)
@@ -893,8 +904,9 @@ hipError_t launch_unshuffle_eb(const StagedArgs& a, bool odd, uint32_t* keys, ui
   sc.b1 = uint32_t(__builtin_ctz(tiles));
   sc.b2 = 0;
   hipLaunchKernelGGL(staged_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, sc);
-  hipLaunchKernelGGL((staged_unshuffle_first_kernel<EB>), dim3(tiles), dim3(S::kThreads), 0, stream, a, keys,
-                     tile_cnt, tile_base);
+  const uint32_t groups = (tiles + kKeysPerTile<EB> - 1) / kKeysPerTile<EB>;
+  hipLaunchKernelGGL((staged_unshuffle_first_kernel<EB>), dim3(groups), dim3(S::kThreads), 0, stream, a, keys,
+                     tile_cnt, tile_base, tiles);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_staged_rest<EB>(a, num_cus, stream);
@@ -904,11 +916,11 @@ hipError_t launch_unshuffle_eb(const StagedArgs& a, bool odd, uint32_t* keys, ui
 
 uint32_t unshuffle_key_tile(uint32_t elem_bytes) {
   switch (elem_bytes) {
-    case 1: return DistShape<1, 3>::kTile;
-    case 2: return DistShape<2, 3>::kTile;
-    case 4: return DistShape<4, 3>::kTile;
-    case 8: return DistShape<8, 3>::kTile;
-    case 16: return DistShape<16, 3>::kTile;
+    case 1: return kKeyTile<1>;
+    case 2: return kKeyTile<2>;
+    case 4: return kKeyTile<4>;
+    case 8: return kKeyTile<8>;
+    case 16: return kKeyTile<16>;
     default: return 0;
   }
 }

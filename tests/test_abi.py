@@ -355,7 +355,9 @@ def test_unshuffle_staged_scratch_sizes_and_argument_checks():
     # and two words per tile of 8,192 padded indices (2^15 tiles)
     n = (1 << 27) + 1
     assert B.bs_unshuffle_staged_scratch_bytes(n, 4) == B.bs_staged_scratch_bytes(n, 4) + 4 * (1 << 28) + 8 * (1 << 15)
-    # 16-byte records: tiles of 4,096 padded indices
+    # 8- and 16-byte records: tiles of 8,192 and 4,096 padded indices
+    assert B.bs_unshuffle_staged_scratch_bytes(n, 8) == (B.bs_staged_scratch_bytes(n, 8) + 4 * (1 << 28)
+                                                          + 8 * (1 << 15))
     assert B.bs_unshuffle_staged_scratch_bytes(n, 16) == (B.bs_staged_scratch_bytes(n, 16) + 4 * (1 << 28)
                                                            + 8 * (1 << 16))
     # a domain smaller than one tile: one tile's key words, one count and prefix
