@@ -97,6 +97,20 @@ int main(void) {
     return 1;
   }
 
+  /* and through the staged streaming passes, with their own caller scratch */
+  void *st_scratch = NULL;
+  const size_t st_bytes = bs_unshuffle_staged_scratch_bytes(n, 4);
+  CHECK_HIP(hipMalloc(&st_scratch, st_bytes));
+  CHECK_HIP(hipMemset(d_back, 0, n * 4));
+  CHECK_BS(bs_unshuffle_staged(d_out, d_back, n, 4, 77, rounds, st_scratch, st_bytes, NULL));
+  CHECK_HIP(hipDeviceSynchronize());
+  CHECK_HIP(hipMemcpy(h_out, d_back, n * 4, hipMemcpyDeviceToHost));
+  if (memcmp(h_out, h_in, n * 4) != 0) {
+    fprintf(stderr, "bs_unshuffle_staged did not give the input back\n");
+    return 1;
+  }
+  CHECK_HIP(hipFree(st_scratch));
+
   /* the bijection alone: f then f^-1 is the identity on [0, 2^21) */
   enum { kVals = 4096 };
   uint64_t vals[kVals], back[kVals];
