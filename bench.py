@@ -118,6 +118,9 @@ def parse_args():
                    help="profiler run: a copy of known size, then --steps staged shuffles of the headline workload "
                         "(and of n = 10^9 uint32 with --staged-large); no extras")
     p.add_argument("--staged-large", action="store_true")
+    p.add_argument("--profile-unshuffle", action="store_true",
+                   help="profiler run: --steps staged un-shuffles (bs_unshuffle_staged) of the headline workload's "
+                        "shuffled output; no extras")
     p.add_argument("--profile-large", action="store_true",
                    help="profiler run: a copy of known size, then the large workloads (10^9 uint32, 2.5e8 x 16 B) "
                         "and the u64 n = 2^27+1 shuffle, --steps each; no extras")
@@ -813,6 +816,19 @@ def main() -> int:
         print(json.dumps({"launch": res}), flush=True)
         return 0
 
+    if args.profile_unshuffle:
+        x = torch.from_numpy(W.uniform_u32(N_HEADLINE, seed=SEED)).to(dev)
+        shuffled = bs.shuffle(x, SEED, rounds)
+        back = torch.empty_like(x)
+        scratch = torch.empty(bs.unshuffle_staged_scratch_bytes(N_HEADLINE, 4), dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup + args.steps):
+            bs.unshuffle_staged(shuffled, SEED, rounds, out=back, scratch=scratch)
+        torch.cuda.synchronize()
+        if not torch.equal(back, x):
+            log("bench: the staged un-shuffle did not give the input back")
+            return 1
+        log(f"bench: {args.warmup + args.steps} staged un-shuffles of n={N_HEADLINE}")
+        return 0
     if args.profile_staged:
         n = 10**9 if args.staged_large else N_HEADLINE
         x = torch.from_numpy(W.uniform_u32(n, seed=SEED)).to(dev)
